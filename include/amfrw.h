@@ -1,0 +1,187 @@
+/*
+ * amfrw.h -- C ABI of libamfrw: AMFR-W time stepping on every component grid of the (modified)
+ * sparse-grid combination technique for the SABR-LIBOR market model PDE, on AMD Instinct MI355X
+ * (gfx950).  Method: Lopez-Salas, Perez-Rodriguez, Vazquez, "AMFR-W numerical methods for solving
+ * high dimensional SABR/LIBOR PDE models", arXiv 2408.00559.
+ *
+ * Conventions shared by every call
+ *   - Every call returns amf_status; nothing throws or aborts across the ABI.  On failure
+ *     amf_last_error() returns a message (thread-local, valid until the next call on the thread).
+ *   - Streams are passed as `void*` and are hipStream_t handles (0 = the null stream).  Enqueueing
+ *     calls are asynchronous: results are valid once the stream has been synchronised.
+ *   - Device memory is caller-owned.  A plan keeps host metadata only; its device state lives in
+ *     one workspace of amf_plan_info.workspace_bytes bytes bound with amf_plan_bind, which must stay
+ *     allocated until all enqueued work that uses it has completed.
+ *   - A plan is not used from two host threads at once.  Plans never share device memory.
+ *   - Grid vectors on the device hold INNER nodes only (every index j_i in 1..M_i, Section 3 of the
+ *     paper), in the plan precision, axis 1 fastest: the element of unit u at multi-index j sits at
+ *     unit_offset(u) + sum_i (j_i - 1) * prod_{k<i} M_k.  Lower-face (Outer) values are implied:
+ *     the payoff for solution vectors, 0 for stage increments.  Axis d-1 is the volatility V.
+ */
+#ifndef AMFRW_H
+#define AMFRW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define AMF_ABI_VERSION 1
+#define AMF_MAX_D 8        /* descriptor capacity; kernels are built for d = 2..6 */
+#define AMF_MAX_STAGES 6
+
+typedef enum {
+    AMF_OK = 0,
+    AMF_E_INVALID = 1,     /* a descriptor or argument is out of range          */
+    AMF_E_UNSUPPORTED = 2, /* valid request this build does not implement        */
+    AMF_E_NOMEM = 3,       /* host allocation failed                             */
+    AMF_E_HIP = 4,         /* a HIP runtime call or kernel launch failed         */
+    AMF_E_NUMERIC = 5,     /* non-finite result (results are still written)      */
+    AMF_E_STATE = 6        /* call order violated (e.g. solve before bind)       */
+} amf_status;
+
+typedef enum { AMF_FP64 = 0, AMF_FP32 = 1 } amf_precision;
+
+typedef enum {
+    AMF_PAYOFF_CAPLET = 0,   /* tau_1 (F_1 - K)^+ (Section 2)                                    */
+    AMF_PAYOFF_SWAPTION = 1  /* max{ sum_i tau_i (F_i - K) / prod_{l<=i} (1 + tau_l F_l), 0 }   */
+} amf_payoff;
+
+/* One pricing instance: the data of the PDE (mmNd) in time-to-maturity form, with coefficients
+ * (coef_diff), (coef_mix), (coef_adv), the domain of Section 3 and the boundary conditions (bound1):
+ * Dirichlet payoff on the lower faces, homogeneous Neumann on the upper faces.  Copied at
+ * amf_plan_create; the caller may free it afterwards. */
+typedef struct {
+    uint32_t struct_size;                       /* = sizeof(amf_problem)                          */
+    int32_t d;                                  /* N: d-1 forward rates plus V, 2 <= d <= 6      */
+    int32_t payoff;                             /* amf_payoff                                     */
+    int32_t reserved;
+    double beta;                                /* elasticity, 0 <= beta <= 1                     */
+    double sigma;                               /* volatility of V (>= 0)                         */
+    double alpha[AMF_MAX_D - 1];                /* alpha_i >= 0                                   */
+    double phi[AMF_MAX_D - 1];                  /* F_i - V correlation, |phi_i| <= 1             */
+    double tau[AMF_MAX_D - 1];                  /* accrual periods tau_i >= 0                     */
+    double rho[(AMF_MAX_D - 1) * (AMF_MAX_D - 1)]; /* rho[i*(AMF_MAX_D-1)+j], unit diagonal      */
+    double x_max[AMF_MAX_D];                    /* F_1^max .. F_{d-1}^max, V^max (> 0)           */
+    double maturity;                            /* T > 0, the PDE horizon                         */
+    double strike;                              /* K                                              */
+    double x_eval[AMF_MAX_D];                   /* evaluation point, inside the domain            */
+    double discount;                            /* price = discount * u(T, x_eval)                */
+} amf_problem;
+
+/* s-stage AMFR-W method: eq (row-s) with the W of eq (Wmat1), stages as eq (amfrw).  a and q are
+ * stored row-major [r*AMF_MAX_STAGES + j] for j < r.  This build runs s = 2. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t stages;
+    double a[AMF_MAX_STAGES * AMF_MAX_STAGES];
+    double q[AMF_MAX_STAGES * AMF_MAX_STAGES];
+    double b[AMF_MAX_STAGES];
+    double theta;
+    double nu;                                  /* AMF parameter of (Wmat1)                       */
+} amf_scheme;
+
+/* Either one full grid (M_i = 2^levels[i]) or the combination technique at level n with offset psi:
+ * eq (standardCombTechnique) for psi = 0, eq (modifiedCombTechnique) for psi > 0. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t full_grid;                          /* 1: levels[] is used; 0: n and psi are used     */
+    int32_t levels[AMF_MAX_D];                  /* 0 <= level <= 16                               */
+    int32_t n;                                  /* n >= d - 1 (coefficients then sum to 1)       */
+    int32_t psi;                                /* 0 <= psi <= 8                                  */
+} amf_grid_spec;
+
+typedef struct amf_plan amf_plan;
+
+typedef struct {
+    int64_t n_problems;
+    int64_t n_units;                  /* (problem, component grid) pairs                           */
+    int64_t inner_points;             /* sum over units of prod M_i                                */
+    int64_t stage_updates_per_solve;  /* inner_points * stages * steps (x3 with Richardson)        */
+    uint64_t workspace_bytes;
+    uint64_t state_offset;            /* byte offset of the state vector Y inside the workspace   */
+    uint64_t vector_bytes;            /* bytes of one grid vector (all units)                      */
+    int32_t d;
+    int32_t precision;                /* amf_precision                                             */
+    int32_t n_steps;
+    int32_t richardson;
+} amf_plan_info;
+
+/* ABI version of the library (AMF_ABI_VERSION). */
+int32_t amf_abi_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* amf_last_error(void);
+
+/* The paper's AMFR-W2 (coef_W2): a21 = 2/3, q21 = -4/3, b = (5/4, 3/4), theta = (3 + sqrt 3)/6,
+ * third order; nu = theta (the paper leaves nu unprinted; nu = theta reproduces its tables). */
+amf_status amf_scheme_amfrw2(amf_scheme* out);
+
+/* Build a plan: enumerate the component grids of `grid` for each of the n_probs problems (all with
+ * the same d), lay out the device workspace, tabulate the 1-D coefficient factors of (coef_diff),
+ * (coef_mix), (coef_adv) in FP64 and round them once to the plan precision.  dt = maturity/n_steps
+ * per problem.  richardson = 1 also runs 2*n_steps and combines prices as (8 P_fine - P_coarse)/7
+ * (fourth order in time from the third-order scheme).  Errors: AMF_E_INVALID for out-of-range
+ * descriptors (d, levels, n < d-1, psi, beta, correlations, x_eval outside the domain, steps < 1),
+ * AMF_E_UNSUPPORTED for stages != 2. */
+amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_grid_spec* grid,
+                           const amf_scheme* scheme, amf_precision precision, int32_t n_steps,
+                           int32_t richardson, amf_plan** out);
+
+/* Sizes and offsets of a plan. */
+amf_status amf_plan_info_get(const amf_plan* plan, amf_plan_info* out);
+
+/* Host metadata of one unit: problem index, levels (d entries), combination coefficient and the
+ * element offset of the unit in every grid vector.  Any pointer may be NULL. */
+amf_status amf_unit_info(const amf_plan* plan, int64_t unit, int32_t* problem, int32_t* levels,
+                         double* coef, int64_t* offset);
+
+/* Bind caller-owned device memory (>= workspace_bytes, 256-byte aligned) and upload the plan's
+ * tables on `stream` (the call synchronises the stream before returning).  Rebinding is allowed
+ * and invalidates the state. */
+amf_status amf_plan_bind(amf_plan* plan, void* d_workspace, uint64_t bytes, void* stream);
+
+/* Initial data (dis0): Y = payoff at every inner node of every unit; resets the step counter. */
+amf_status amf_init(amf_plan* plan, void* stream);
+
+/* Advance every unit by n AMFR-W steps (eq amfrw): per stage the explicit operator of Sketch 1,
+ * the AMF chain of directional tridiagonal solves (Lemma lema:ls) along axes 1..d, the refinement
+ * 2K - (I - theta dt F')K^(d) with F'K = F(K), a second chain, then Y += sum b_r K_r. */
+amf_status amf_time_step(amf_plan* plan, int32_t n, void* stream);
+
+/* amf_init + n_steps steps (and the 2*n_steps fine run when richardson = 1). */
+amf_status amf_solve(amf_plan* plan, void* stream);
+
+/* Per-unit value u_l(x_eval) by tensor-product linear interpolation (Section 5), in FP64, one per
+ * unit in unit order, written to d_values (device, n_units doubles). */
+amf_status amf_unit_values(amf_plan* plan, double* d_values, void* stream);
+
+/* Prices: per problem, discount * sum_l c_l u_l(x_eval) in FP64 over its units in unit order
+ * (eq modifiedCombTechnique), written to d_prices (device, n_problems doubles).  With Richardson,
+ * the extrapolated price.  Returns AMF_E_NUMERIC (after the stream completes) if a price is not
+ * finite. */
+amf_status amf_combine(amf_plan* plan, double* d_prices, void* stream);
+
+/* Device pointer of the plan's solution vector Y (inner-node layout above, plan precision). */
+amf_status amf_state_ptr(const amf_plan* plan, void** d_state);
+
+/* Step-level entry points (parity testing of the individual steps).  d_in / d_out are grid vectors
+ * in the inner-node layout and the plan precision, distinct from the workspace.
+ *   amf_apply_operator: d_out = scale * F(d_in) of Sketch 1 on every unit; lower-face values are
+ *     the payoff (increment = 0) or 0 (increment = 1).  d_in and d_out must not overlap.
+ *   amf_axis_solve: solve (I - nu dt A_axis) d_out = d_in for every unit (Lemma lema:ls), with
+ *     A_axis the directional second-difference matrix of (ffis) and nu, dt from the plan.
+ *     d_out may equal d_in. */
+amf_status amf_apply_operator(amf_plan* plan, const void* d_in, void* d_out, int32_t increment,
+                              double scale, void* stream);
+amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* d_out, void* stream);
+
+/* Release host resources.  Device memory stays owned by the caller.  NULL is allowed. */
+void amf_plan_destroy(amf_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMFRW_H */

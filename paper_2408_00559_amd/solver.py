@@ -1,0 +1,177 @@
+"""Python front end of libamfrw: marshals `inputs.Problem` / `inputs.GridSpec` into the C ABI and
+owns the device workspace as a torch tensor.  Every step of the method runs in the HIP kernels."""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Sequence
+
+import torch
+
+from . import _lib as L
+from .inputs import CAPLET, GridSpec, Problem
+
+PAYOFF = {CAPLET: L.PAYOFF_CAPLET, "swaption": L.PAYOFF_SWAPTION}
+
+
+def problem_struct(p: Problem) -> L.AmfProblem:
+    s = L.AmfProblem()
+    s.struct_size = C.sizeof(L.AmfProblem)
+    s.d = p.d
+    s.payoff = PAYOFF[p.payoff]
+    s.beta = p.beta
+    s.sigma = p.sigma
+    for i in range(p.d - 1):
+        s.alpha[i] = p.alpha[i]
+        s.phi[i] = p.phi[i]
+        s.tau[i] = p.tau[i]
+        for k in range(p.d - 1):
+            s.rho[i * L.RHO_LD + k] = p.rho[i][k]
+    for i in range(p.d):
+        s.x_max[i] = p.xmax[i]
+        s.x_eval[i] = p.xeval[i]
+    s.maturity = p.T
+    s.strike = p.K
+    s.discount = p.discount
+    return s
+
+
+def grid_struct(g: GridSpec) -> L.AmfGridSpec:
+    s = L.AmfGridSpec()
+    s.struct_size = C.sizeof(L.AmfGridSpec)
+    s.full_grid = 1 if g.full else 0
+    if g.full:
+        for i, l in enumerate(g.levels):
+            s.levels[i] = l
+    s.n = g.n
+    s.psi = g.psi
+    return s
+
+
+def scheme_amfrw2(nu: float | None = None) -> L.AmfScheme:
+    s = L.AmfScheme()
+    L.check(L.lib().amf_scheme_amfrw2(C.byref(s)))
+    if nu is not None:
+        s.nu = nu
+    return s
+
+
+def _stream(stream=None) -> C.c_void_p:
+    st = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(st.cuda_stream)
+
+
+class Plan:
+    """A bound plan: problems x component grids, the workspace on `device`, and the solve calls."""
+
+    def __init__(self, problems: Sequence[Problem], grid: GridSpec, steps: int, precision: str = "fp64",
+                 richardson: bool = False, scheme: L.AmfScheme | None = None, device: str = "cuda:0"):
+        lib = L.lib()
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (L.AmfProblem * n)(*[problem_struct(p) for p in self.problems])
+        gs = grid_struct(grid)
+        sc = scheme if scheme is not None else scheme_amfrw2()
+        self.precision = precision
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        prec = L.FP64 if precision == "fp64" else L.FP32
+        h = C.c_void_p()
+        L.check(lib.amf_plan_create(arr, n, C.byref(gs), C.byref(sc), prec, int(steps),
+                                    1 if richardson else 0, C.byref(h)))
+        self._h = h
+        self.info = L.AmfPlanInfo()
+        L.check(lib.amf_plan_info_get(h, C.byref(self.info)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(self.info.workspace_bytes) + 256, dtype=torch.uint8,
+                                     device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_off = (-base) % 256
+        with torch.cuda.device(self.device):
+            L.check(lib.amf_plan_bind(h, C.c_void_p(base + self._ws_off), int(self.info.workspace_bytes),
+                                      _stream()))
+
+    # -- metadata -------------------------------------------------------------------------------
+    @property
+    def n_units(self) -> int:
+        return int(self.info.n_units)
+
+    @property
+    def inner_points(self) -> int:
+        return int(self.info.inner_points)
+
+    @property
+    def stage_updates(self) -> int:
+        return int(self.info.stage_updates_per_solve)
+
+    def unit(self, u: int):
+        prob = C.c_int32()
+        lv = (C.c_int32 * L.MAX_D)()
+        cf = C.c_double()
+        off = C.c_int64()
+        L.check(L.lib().amf_unit_info(self._h, int(u), C.byref(prob), lv, C.byref(cf), C.byref(off)))
+        d = int(self.info.d)
+        return dict(problem=prob.value, levels=[lv[i] for i in range(d)], coef=cf.value, offset=off.value)
+
+    def units(self) -> List[dict]:
+        return [self.unit(u) for u in range(self.n_units)]
+
+    # -- calls ----------------------------------------------------------------------------------
+    def init(self, stream=None):
+        L.check(L.lib().amf_init(self._h, _stream(stream)))
+
+    def time_step(self, n: int, stream=None):
+        L.check(L.lib().amf_time_step(self._h, int(n), _stream(stream)))
+
+    def solve(self, stream=None):
+        L.check(L.lib().amf_solve(self._h, _stream(stream)))
+
+    def combine(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(len(self.problems), dtype=torch.float64, device=self.device)
+        L.check(L.lib().amf_combine(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def unit_values(self, stream=None) -> torch.Tensor:
+        out = torch.empty(self.n_units, dtype=torch.float64, device=self.device)
+        L.check(L.lib().amf_unit_values(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def state(self) -> torch.Tensor:
+        """View of the solution vector Y (inner-node layout, plan precision)."""
+        off = self._ws_off + int(self.info.state_offset)
+        nb = int(self.info.vector_bytes)
+        return self.workspace[off:off + nb].view(self.dtype)
+
+    def apply_operator(self, x: torch.Tensor, increment: bool, scale: float = 1.0, stream=None) -> torch.Tensor:
+        assert x.dtype == self.dtype and x.numel() == self.inner_points and x.is_contiguous()
+        out = torch.empty_like(x)
+        L.check(L.lib().amf_apply_operator(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
+                                           1 if increment else 0, float(scale), _stream(stream)))
+        return out
+
+    def axis_solve(self, axis: int, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        assert x.dtype == self.dtype and x.numel() == self.inner_points and x.is_contiguous()
+        if out is None:
+            out = torch.empty_like(x)
+        L.check(L.lib().amf_axis_solve(self._h, int(axis), C.c_void_p(x.data_ptr()),
+                                       C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def price(self, stream=None) -> torch.Tensor:
+        self.solve(stream)
+        return self.combine(stream=stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().amf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_for(workload: dict, precision: str = "fp64", **kw) -> Plan:
+    return Plan(workload["problems"], workload["grid"], workload["steps"], precision=precision,
+                richardson=kw.pop("richardson", workload.get("richardson", False)), **kw)

@@ -1,0 +1,191 @@
+"""GPU parity: every step of the HIP path against the FP64 CPU oracle, element by element, through
+the C ABI.  FP64 bar: 1e-10 relative (prices) and 1e-12 of the vector's max-norm for single
+operator applications; FP32 bar: 1e-5 relative per price."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2408_00559_amd import inputs as I
+from paper_2408_00559_amd.solver import Plan
+
+from _util import parallel, rel_maxerr, unit_slices
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _cases():
+    d3 = I.draw_instances(2, seed=31, d=3)
+    d4 = I.draw_instances(3, seed=41, d=4)
+    d5 = I.draw_instances(1, seed=51, d=5)
+    d6 = I.draw_instances(1, seed=61, d=6)
+    return {
+        "fg2d": (I.workload_fg2d()["problems"], I.full_grid([6, 6])),
+        "long_rate_axis": (I.workload_fg2d()["problems"], I.full_grid([10, 3])),
+        "long_v_axis": (I.workload_fg2d()["problems"], I.full_grid([3, 10])),
+        "d3_full_ragged": (d3[:1], I.full_grid([7, 0, 8])),
+        "d2_standard_ct": ([I.paper_caplet(sigma=0.3, phi=0.4)], I.combination(6, 0)),
+        "d3_ct": (d3, I.combination(4, 1)),
+        "d4_ct": (d4, I.combination(4, 1)),
+        "d5_ct": (d5, I.combination(4, 1)),
+        "d6_ct": (d6, I.combination(5, 1)),
+    }
+
+
+CASES = _cases()
+
+
+def _random_inner(plan, seed):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, plan.inner_points)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_initial_data(name):
+    probs, grid = CASES[name]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    plan.init()
+    Y = plan.state().cpu().numpy()
+    for u, sl in unit_slices(plan):
+        p = probs[u["problem"]]
+        ref = oracle.inner_view(oracle.initial_data(p, u["levels"]), u["levels"])
+        np.testing.assert_allclose(Y[sl], ref, rtol=1e-15, atol=1e-18)
+
+
+@pytest.mark.parametrize("increment", [False, True])
+@pytest.mark.parametrize("name", list(CASES))
+def test_operator_sketch1(name, increment):
+    """a3: F(Y) of Sketch 1 on a random vector, lower faces = payoff (solution) or 0 (increment)."""
+    probs, grid = CASES[name]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    x = _random_inner(plan, 7)
+    out = plan.apply_operator(torch.tensor(x, device=DEV), increment=increment, scale=0.5).cpu().numpy()
+    for u, sl in unit_slices(plan):
+        p = probs[u["problem"]]
+        lv = u["levels"]
+        outer = None if increment else oracle.initial_data(p, lv)
+        full = oracle.full_from_inner(x[sl], lv, outer_value=0.0, outer_from=outer)
+        ref = 0.5 * oracle.inner_view(oracle.eval_F(p, lv, full), lv)
+        assert rel_maxerr(out[sl], ref) < 1e-12, (u, rel_maxerr(out[sl], ref))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_axis_solves(name):
+    """a4: (I - nu dt A_i) K = G along every axis (Lemma lema:ls), in place and out of place."""
+    probs, grid = CASES[name]
+    steps = 3
+    plan = Plan(probs, grid, steps=steps, device=DEV)
+    theta = (3 + math.sqrt(3)) / 6
+    g = _random_inner(plan, 11)
+    gt = torch.tensor(g, device=DEV)
+    for ax in range(probs[0].d):
+        out = plan.axis_solve(ax, gt).cpu().numpy()
+        inplace = gt.clone()
+        plan.axis_solve(ax, inplace, out=inplace)
+        assert np.array_equal(out, inplace.cpu().numpy())
+        for u, sl in unit_slices(plan):
+            p = probs[u["problem"]]
+            lv = u["levels"]
+            full = oracle.full_from_inner(g[sl], lv)
+            ref = oracle.inner_view(oracle.solve_axis(p, lv, ax, theta * p.T / steps, full), lv)
+            # Thomas rounding grows with the line length M: bound ~ M eps
+            tol = max(1e-13, 4e-16 * (1 << lv[ax]))
+            assert rel_maxerr(out[sl], ref) < tol, (ax, u)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_one_step(name):
+    """a3-a6 together: one AMFR-W2 step from the payoff, every inner node of every unit."""
+    probs, grid = CASES[name]
+    steps = 5
+    plan = Plan(probs, grid, steps=steps, device=DEV)
+    plan.init()
+    plan.time_step(1)
+    Y = plan.state().cpu().numpy()
+
+    def ref(item):
+        u, sl = item
+        p = probs[u["problem"]]
+        lv = u["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / steps, 1)
+        return oracle.inner_view(Yf, lv)
+
+    items = unit_slices(plan)
+    for (u, sl), r in zip(items, parallel(ref, items)):
+        assert rel_maxerr(Y[sl], r) < 1e-12, u
+
+
+def test_full_grid_fg2d_fp64():
+    """d = 2 full grid 65 x 65, 50 steps, FP64: every node and the price within 1e-10."""
+    w = I.workload_fg2d()
+    p = w["problems"][0]
+    plan = Plan(w["problems"], w["grid"], w["steps"], device=DEV)
+    price = plan.price().cpu().numpy()[0]
+    ref_full = oracle.solve_grid(p, w["grid"].levels, w["steps"])
+    ref_price = oracle.price(p, w["grid"], w["steps"])
+    assert abs(price - ref_price) / abs(ref_price) < 1e-10, (price, ref_price)
+    Y = plan.state().cpu().numpy()
+    assert rel_maxerr(Y, oracle.inner_view(ref_full, w["grid"].levels)) < 1e-10
+
+
+def test_paper_tables_on_gpu():
+    """The GPU path reproduces printed table entries: Table fg_2d level 6 (6.050103 bps) and Table
+    d2_1 n = 6 at 256 steps (6.052738 bps, includes level-0 axes with one inner node)."""
+    plan = Plan([I.paper_caplet(sigma=0.3, phi=0.4)], I.full_grid([6, 6]), 256, device=DEV)
+    assert abs(plan.price().item() * 1e4 - 6.050103) < 1e-6
+    plan = Plan([I.paper_caplet()], I.combination(6, 0), 256, device=DEV)
+    assert abs(plan.price().item() * 1e4 - 6.052738) < 1e-6
+    plan = Plan([I.paper_caplet()], I.combination(7, 2), 256, device=DEV)
+    assert abs(plan.price().item() * 1e4 - 6.057952) < 1e-6
+
+
+@pytest.mark.parametrize("d,n,psi,steps,count", [(3, 5, 1, 20, 2), (4, 4, 1, 10, 3), (5, 4, 1, 6, 1),
+                                                 (6, 5, 1, 2, 1)])
+def test_combination_prices_fp64(d, n, psi, steps, count):
+    """a7-a8: several problems in one plan, each priced by the modified combination technique."""
+    probs = I.draw_instances(count, seed=100 + d, d=d)
+    grid = I.combination(n, psi)
+    plan = Plan(probs, grid, steps, device=DEV)
+    prices = plan.price().cpu().numpy()
+    vals = plan.unit_values().cpu().numpy()
+    refs = parallel(lambda p: oracle.price(p, grid, steps, nthreads=1, return_units=True), probs)
+    nu = len(vals) // count
+    for i, (rp, ru) in enumerate(refs):
+        assert abs(prices[i] - rp) / abs(rp) < 1e-10, (i, prices[i], rp)
+        assert rel_maxerr(vals[i * nu:(i + 1) * nu], ru) < 1e-10
+
+
+def test_richardson_fp64():
+    probs = I.draw_instances(1, seed=7, d=3)
+    grid = I.combination(4, 1)
+    plan = Plan(probs, grid, 6, richardson=True, device=DEV)
+    price = plan.price().item()
+    ref = oracle.price(probs[0], grid, 6, richardson=True)
+    assert abs(price - ref) / abs(ref) < 1e-10
+
+
+def test_fp32_fg2d():
+    """FP32 stencil and sweeps, FP64 interpolation/combination: within 1e-5 of the FP64 oracle."""
+    w = I.workload_fg2d()
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp32", device=DEV)
+    price = plan.price().item()
+    ref = oracle.price(w["problems"][0], w["grid"], w["steps"])
+    assert abs(price - ref) / abs(ref) < 1e-5, (price, ref)
+
+
+def test_determinism_and_restart():
+    """Bitwise-identical reruns; time_step(2) + time_step(3) equals time_step(5)."""
+    probs = I.draw_instances(2, seed=5, d=4)
+    plan = Plan(probs, I.combination(4, 1), 5, device=DEV)
+    a = plan.price().cpu().numpy()
+    b = plan.price().cpu().numpy()
+    assert np.array_equal(a, b)
+    plan.init()
+    plan.time_step(2)
+    plan.time_step(3)
+    c = plan.combine().cpu().numpy()
+    assert np.array_equal(a, c)

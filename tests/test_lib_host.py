@@ -1,0 +1,136 @@
+"""Host-side checks of libamfrw that need no GPU: the library loads, exports every symbol the
+header declares, validates descriptors, and enumerates the combination technique's grids exactly as
+the paper's formula (cross-checked against the oracle's independent enumeration)."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2408_00559_amd import _lib as L
+from paper_2408_00559_amd import inputs as I
+from paper_2408_00559_amd import solver as S
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "amfrw.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(amf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+    assert lib.amf_abi_version() == 1
+
+
+def _create(probs, grid, steps=10, prec=L.FP64, rich=0, scheme=None):
+    lib = L.lib()
+    arr = (L.AmfProblem * len(probs))(*[S.problem_struct(p) for p in probs])
+    gs = S.grid_struct(grid)
+    sc = scheme or S.scheme_amfrw2()
+    h = C.c_void_p()
+    st = lib.amf_plan_create(arr, len(probs), C.byref(gs), C.byref(sc), prec, steps, rich, C.byref(h))
+    return st, h
+
+
+def test_scheme_coefficients():
+    s = S.scheme_amfrw2()
+    assert s.stages == 2
+    assert s.a[1 * 6 + 0] == 2.0 / 3.0 and s.q[1 * 6 + 0] == -4.0 / 3.0
+    assert (s.b[0], s.b[1]) == (1.25, 0.75)
+    assert abs(s.theta - (3 + math.sqrt(3)) / 6) < 1e-16 and s.nu == s.theta
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda p: setattr(p, "beta", 1.5), L.E_INVALID),
+    (lambda p: setattr(p, "sigma", -0.1), L.E_INVALID),
+    (lambda p: setattr(p, "T", 0.0), L.E_INVALID),
+    (lambda p: p.xeval.__setitem__(0, 0.5), L.E_INVALID),
+    (lambda p: p.phi.__setitem__(0, 1.5), L.E_INVALID),
+    (lambda p: p.rho[0].__setitem__(1, 0.3), L.E_INVALID),     # asymmetric
+    (lambda p: p.xmax.__setitem__(1, 0.0), L.E_INVALID),
+])
+def test_invalid_problems_rejected(mutate, status):
+    p = I.draw_instances(1, seed=1, d=3)[0]
+    mutate(p)
+    st, h = _create([p], I.combination(4, 1))
+    assert st == status, L.lib().amf_last_error()
+    assert not h.value
+    assert len(L.lib().amf_last_error()) > 0
+
+
+def test_invalid_grid_and_scheme():
+    p = I.draw_instances(1, seed=1, d=4)[0]
+    assert _create([p], I.combination(2, 1))[0] == L.E_INVALID          # n < d - 1
+    assert _create([p], I.combination(5, -1))[0] == L.E_INVALID
+    assert _create([p], I.full_grid([20, 1, 1, 1]))[0] == L.E_INVALID
+    assert _create([p], I.combination(5, 1), steps=0)[0] == L.E_INVALID
+    sc = S.scheme_amfrw2()
+    sc.stages = 3
+    assert _create([p], I.combination(5, 1), scheme=sc)[0] == L.E_UNSUPPORTED
+    q = I.draw_instances(1, seed=1, d=3)[0]
+    assert _create([p, q], I.combination(5, 1))[0] == L.E_INVALID      # mixed d
+    p7 = I.draw_instances(1, seed=1, d=7)[0]
+    assert _create([p7], I.combination(7, 1))[0] == L.E_INVALID
+
+
+@pytest.mark.parametrize("d,n,psi", [(2, 6, 0), (3, 8, 1), (4, 7, 3), (6, 8, 1), (4, 6, 1)])
+def test_units_match_combination_formula(orc, d, n, psi):
+    probs = I.draw_instances(2, seed=3, d=d)
+    plan_st, h = _create(probs, I.combination(n, psi))
+    assert plan_st == L.OK
+    lib = L.lib()
+    info = L.AmfPlanInfo()
+    L.check(lib.amf_plan_info_get(h, C.byref(info)))
+    olv, ocf = orc.ct_grids(d, n, psi)
+    assert info.n_units == 2 * len(ocf)
+    total = 0
+    for u in range(info.n_units):
+        prob = C.c_int32()
+        lv = (C.c_int32 * 8)()
+        cf = C.c_double()
+        off = C.c_int64()
+        L.check(lib.amf_unit_info(h, u, C.byref(prob), lv, C.byref(cf), C.byref(off)))
+        g = u % len(ocf)
+        assert prob.value == u // len(ocf)
+        assert [lv[i] for i in range(d)] == list(olv[g])
+        assert cf.value == ocf[g]
+        assert off.value == total
+        total += 1 << int(sum(olv[g]))
+    assert info.inner_points == total
+    assert info.stage_updates_per_solve == total * 2 * 10
+    lib.amf_plan_destroy(h)
+
+
+def test_workload_sizes():
+    """Inner-point counts of the benchmark workloads (d=4 n=7 psi=3; d=6 n=8 psi=1)."""
+    st, h = _create(I.workload_ct4()["problems"], I.workload_ct4()["grid"], steps=100)
+    info = L.AmfPlanInfo()
+    L.check(L.lib().amf_plan_info_get(h, C.byref(info)))
+    assert (info.n_units, info.inner_points) == (295, 94568448)
+    L.lib().amf_plan_destroy(h)
+    w = I.workload_ct6()
+    st, h = _create(w["problems"], w["grid"], steps=200, prec=L.FP32, rich=1)
+    L.check(L.lib().amf_plan_info_get(h, C.byref(info)))
+    assert (info.n_units, info.inner_points) == (2975, 30140416)
+    assert info.stage_updates_per_solve == 30140416 * 2 * 200 * 3
+    L.lib().amf_plan_destroy(h)
+
+
+def test_state_calls_need_bound_workspace():
+    p = I.draw_instances(1, seed=1, d=3)[0]
+    st, h = _create([p], I.combination(4, 1))
+    assert st == L.OK
+    assert L.lib().amf_init(h, None) == L.E_STATE
+    assert L.lib().amf_time_step(h, 1, None) == L.E_STATE
+    L.lib().amf_plan_destroy(h)
+    L.lib().amf_plan_destroy(None)
