@@ -1,0 +1,215 @@
+"""Benchmark: grid-point stage-updates/s of the AMFR-W2 + modified-combination solver on one MI355X.
+
+One benchmark step = one whole solve of the d = 4 workload (3 forward rates + V, modified
+combination technique n = 7, psi = 3: 295 component grids, 94.6 M inner points, 100 AMFR-W2 steps)
+followed by the FP64 combination into its price.  Inputs are resident in HBM before timing starts.
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("grid-point stage-updates/s and prices/s at 1e-5 rel err, plain FP64 vs batched "
+          "FP32/surrogate")
+HBM_PEAK_GBPS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2408_00559_amd", "csrc", "amfrw_kernels.hip")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "ct4_n7_psi3_fp64.json")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_for(kernel: str, precision: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_ct4.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except ValueError:
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_hash():
+        return None
+    rec = d.get("per_launch", {}).get(precision, {}).get(kernel)
+    return None if rec is None else rec.get("bytes_per_launch")
+
+
+def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
+    x = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del x, y
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
+def run_form(torch, Plan, w, precision, steps, warmup):
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision=precision, device="cuda:0")
+    prices = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    for _ in range(warmup):
+        plan.solve()
+        plan.combine(prices)
+    torch.cuda.synchronize()
+    plan.profile_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.solve()
+        plan.combine(prices)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kstats = plan.profile_end()
+    sec = (t1 - t0) / steps
+    su = plan.stage_updates
+    price = float(prices.item())
+    # dominant kernel by summed event time
+    dom = max(("stencil", "sweep", "sweep_update"), key=lambda k: kstats[k]["ms"])
+    ks = kstats[dom]
+    achieved = ks["algo_bytes"] / (ks["ms"] * 1e-3) / 1e9 if ks["ms"] > 0 else 0.0
+    launches = max(ks["launches"], 1)
+    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dom, precision),
+            "algo_bytes_per_launch": ks["algo_bytes"] / launches,
+            "avg_launch_us": ks["ms"] * 1e3 / launches, "launches_per_solve": ks["launches"] / steps}
+    per_kernel = {k: {"launches_per_solve": v["launches"] / steps, "ms_per_solve": v["ms"] / steps,
+                      "GBps": (v["algo_bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
+                  for k, v in kstats.items() if v["launches"]}
+    out = dict(value=su / sec, sec_per_solve=sec, price=price, stage_updates=su, roofline=roof,
+               kernels=per_kernel, units=plan.n_units, inner_points=plan.inner_points)
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(w, max_seconds_hint=20.0):
+    """The FP64 oracle on a bounded sample of the same workload: the smallest combination layer
+    (35 component grids of 65,536 inner points) for a few of the 100 time steps, all host cores."""
+    import numpy as np
+
+    import oracle
+
+    p = w["problems"][0]
+    lv, cf = oracle.ct_grids(p.d, w["grid"].n, w["grid"].psi)
+    sums = lv.sum(axis=1)
+    sel = lv[sums == sums.min()]
+    steps = 6
+    threads = oracle.max_threads()
+    sc = oracle.scheme_amfrw2()
+    ps = oracle.problem_struct(p)
+    import ctypes as C
+    L = oracle.lib()
+    lvc = np.ascontiguousarray(sel, dtype=np.int32)
+    coef = np.ones(len(sel))
+    units = np.empty(len(sel))
+    out = np.zeros(1)
+    # dt of the workload (T / 100 steps) and `steps` of them: orc_price_grids solves to T with the
+    # given step count, so scale the maturity to keep dt unchanged.
+    ps.T = p.T * steps / w["steps"]
+    t0 = time.perf_counter()
+    rc = L.orc_price_grids(C.byref(ps), lvc.ctypes.data_as(C.POINTER(C.c_int32)),
+                           coef.ctypes.data_as(C.POINTER(C.c_double)), len(sel), C.byref(sc), steps,
+                           threads, units.ctypes.data_as(C.POINTER(C.c_double)),
+                           out.ctypes.data_as(C.POINTER(C.c_double)))
+    dt = time.perf_counter() - t0
+    assert rc == 0
+    su = float(sum(1 << int(s) for s in sel.sum(axis=1))) * 2 * steps
+    return {"value": su / dt, "unit": "stage-updates/s", "cores": threads, "kind": "oracle",
+            "seconds": dt,
+            "sample": "%d of %d component grids (smallest layer, %d inner points each), %d of %d time "
+                      "steps at the workload's dt, FP64 CPU oracle" % (len(sel), len(lv),
+                                                                      1 << int(sums.min()), steps,
+                                                                      w["steps"]),
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the component grids are independent until the final "
+              "FP64 combination, and this build measures one GPU's share (see DESIGN.md for the "
+              "multi-GPU sharding design).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2408_00559_amd import inputs as I
+    from paper_2408_00559_amd.solver import Plan
+
+    w = I.workload_ct4()
+    copy_gbps = copy_bandwidth(torch)
+    f64 = run_form(torch, Plan, w, "fp64", args.steps, args.warmup)
+    f32 = None if args.no_fp32 else run_form(torch, Plan, w, "fp32", args.steps, args.warmup)
+    golden = json.load(open(GOLDEN)) if os.path.exists(GOLDEN) else None
+    ref = golden["price"] if golden else None
+    res = {
+        "metric": METRIC,
+        "value": f64["value"],
+        "unit": "stage-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": f64["sec_per_solve"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "d": 4, "grid": "modified combination n=7 psi=3",
+                   "component_grids": f64["units"], "inner_points": f64["inner_points"],
+                   "time_steps": w["steps"], "scheme": "AMFR-W2 (nu = theta)",
+                   "stage_updates_per_solve": f64["stage_updates"]},
+        "prices_per_s": 1.0 / f64["sec_per_solve"],
+        "price": f64["price"],
+        "oracle_price": ref,
+        "rel_err_vs_oracle": (abs(f64["price"] - ref) / abs(ref)) if ref else None,
+        "roofline": f64["roofline"],
+        "kernels": f64["kernels"],
+        "copy_GBps": copy_gbps,
+    }
+    if f32 is not None:
+        base = ref if ref else f64["price"]
+        res["fp32"] = {"value": f32["value"], "unit": "stage-updates/s", "dtype": "f32",
+                       "ms_per_step": f32["sec_per_solve"] * 1e3, "prices_per_s": 1.0 / f32["sec_per_solve"],
+                       "price": f32["price"], "rel_err": abs(f32["price"] - base) / abs(base),
+                       "rel_err_against": "oracle" if ref else "fp64 GPU",
+                       "roofline": f32["roofline"], "kernels": f32["kernels"]}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,8 +160,8 @@ amf_status amf_unit_values(amf_plan* plan, double* d_values, void* stream);
 
 /* Prices: per problem, discount * sum_l c_l u_l(x_eval) in FP64 over its units in unit order
  * (eq modifiedCombTechnique), written to d_prices (device, n_problems doubles).  With Richardson,
- * the extrapolated price.  Returns AMF_E_NUMERIC (after the stream completes) if a price is not
- * finite. */
+ * the extrapolated price.  Asynchronous: non-finite prices (an unstable configuration) are written
+ * as they are and are the caller's to detect. */
 amf_status amf_combine(amf_plan* plan, double* d_prices, void* stream);
 
 /* Device pointer of the plan's solution vector Y (inner-node layout above, plan precision). */
@@ -177,6 +177,33 @@ amf_status amf_state_ptr(const amf_plan* plan, void** d_state);
 amf_status amf_apply_operator(amf_plan* plan, const void* d_in, void* d_out, int32_t increment,
                               double scale, void* stream);
 amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* d_out, void* stream);
+
+/* Per-kernel timing (measurement support).  Between amf_profile_begin and amf_profile_end every
+ * kernel the plan launches is bracketed by two HIP events recorded on its launch stream.
+ * amf_profile_end waits for the last event and returns, per kernel class, the launch count, the
+ * summed event time and the summed algorithmic bytes (bytes the kernel must move at minimum:
+ * every vector it reads or writes once, in the plan precision). */
+typedef enum {
+    AMF_K_INIT = 0,        /* payoff initialisation                                    */
+    AMF_K_STENCIL = 1,     /* Sketch-1 operator fused with a stage combination          */
+    AMF_K_SWEEP = 2,       /* directional tridiagonal solves                            */
+    AMF_K_SWEEP_UPDATE = 3,/* last solve of a step fused with Y += b1 K1 + b2 K2        */
+    AMF_K_UNIT_VALUES = 4, /* interpolation at x_eval                                   */
+    AMF_K_COMBINE = 5,     /* FP64 combination                                          */
+    AMF_K_COUNT = 6
+} amf_kernel_class;
+
+typedef struct {
+    int32_t kernel;        /* amf_kernel_class */
+    int32_t reserved;
+    int64_t launches;
+    double total_ms;
+    double algo_bytes;
+} amf_kernel_stat;
+
+amf_status amf_profile_begin(amf_plan* plan);
+/* stats: array of AMF_K_COUNT entries (one per class, in class order). */
+amf_status amf_profile_end(amf_plan* plan, amf_kernel_stat* stats);
 
 /* Release host resources.  Device memory stays owned by the caller.  NULL is allowed. */
 void amf_plan_destroy(amf_plan* plan);

@@ -46,6 +46,15 @@ class AmfPlanInfo(C.Structure):
                 ("precision", C.c_int32), ("n_steps", C.c_int32), ("richardson", C.c_int32)]
 
 
+class AmfKernelStat(C.Structure):
+    _fields_ = [("kernel", C.c_int32), ("reserved", C.c_int32), ("launches", C.c_int64),
+                ("total_ms", C.c_double), ("algo_bytes", C.c_double)]
+
+
+K_NAMES = ["init", "stencil", "sweep", "sweep_update", "unit_values", "combine"]
+K_COUNT = len(K_NAMES)
+
+
 class AmfError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
@@ -95,6 +104,10 @@ def lib():
         L.amf_apply_operator.argtypes = [vp, vp, vp, C.c_int32, C.c_double, vp]
         L.amf_axis_solve.restype = st
         L.amf_axis_solve.argtypes = [vp, C.c_int32, vp, vp, vp]
+        L.amf_profile_begin.restype = st
+        L.amf_profile_begin.argtypes = [vp]
+        L.amf_profile_end.restype = st
+        L.amf_profile_end.argtypes = [vp, C.POINTER(AmfKernelStat)]
         L.amf_plan_destroy.restype = None
         L.amf_plan_destroy.argtypes = [vp]
         _lib = L
@@ -109,4 +122,4 @@ def check(status: int):
 EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_plan_create",
             "amf_plan_info_get", "amf_unit_info", "amf_plan_bind", "amf_init", "amf_time_step",
             "amf_solve", "amf_unit_values", "amf_combine", "amf_state_ptr", "amf_apply_operator",
-            "amf_axis_solve", "amf_plan_destroy"]
+            "amf_axis_solve", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy"]

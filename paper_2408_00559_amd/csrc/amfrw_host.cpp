@@ -58,7 +58,24 @@ struct amf_plan {
     bool bound = false, initialised = false, have_coarse = false;
     DevPlan dev{};
 
+    // per-kernel event timing
+    struct ProfRec {
+        int kclass;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_next = 0;
+    std::vector<ProfRec> recs;
+
     void* vec(int v) const { return ws + off_vec[v]; }
+    double vbytes() const { return (double)total * (double)elem; }
+
+    ~amf_plan()
+    {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    }
 };
 
 namespace {
@@ -484,11 +501,61 @@ amf_status check_bound(const amf_plan* P)
     return AMF_OK;
 }
 
+hipEvent_t pool_event(amf_plan* P)
+{
+    if (P->pool_next == P->pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        P->pool.push_back(e);
+    }
+    return P->pool[P->pool_next++];
+}
+
+// Launch through `fn`, bracketed by events when profiling is on.
+template <class Fn>
+hipError_t timed(amf_plan* P, int kclass, double bytes, hipStream_t s, Fn&& fn)
+{
+    if (!P->prof) return fn();
+    hipEvent_t a = pool_event(P), b = pool_event(P);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    if ((e = fn()) != hipSuccess) return e;
+    if ((e = hipEventRecord(b, s)) != hipSuccess) return e;
+    P->recs.push_back({kclass, a, b, bytes});
+    return hipSuccess;
+}
+
+hipError_t run_stencil(amf_plan* P, int op, const StencilArgs& a, hipStream_t s)
+{
+    const double nv = (op == OP_F_PAYOFF || op == OP_F_ZERO) ? 2.0 : 3.0;
+    return timed(P, AMF_K_STENCIL, nv * P->vbytes(), s,
+                 [&] { return launch_stencil(P->dev, P->prec, op, a, s); });
+}
+
+hipError_t run_sweep(amf_plan* P, int axis, int epi, const SweepArgs& a, hipStream_t s)
+{
+    const bool up = epi == EPI_UPDATE;
+    return timed(P, up ? AMF_K_SWEEP_UPDATE : AMF_K_SWEEP, (up ? 4.0 : 2.0) * P->vbytes(), s,
+                 [&] { return launch_sweep(P->dev, P->prec, axis, epi, a, s); });
+}
+
+hipError_t run_init(amf_plan* P, hipStream_t s)
+{
+    return timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_init(P->dev, P->prec, P->vec(V_Y), s); });
+}
+
+hipError_t run_unit_values(amf_plan* P, double* vals, hipStream_t s)
+{
+    const double b = (double)P->n_units * (double)(1 << P->d) * (double)P->elem + 8.0 * P->n_units;
+    return timed(P, AMF_K_UNIT_VALUES, b, s,
+                 [&] { return launch_unit_values(P->dev, P->prec, P->vec(V_Y), vals, s); });
+}
+
 // One AMFR-W step (eq amfrw) of the 2-stage scheme on every unit.  run selects dt (0: coarse,
 // 1: fine half step of the Richardson pair).
 amf_status one_step(amf_plan* P, int run, hipStream_t s)
 {
-    const DevPlan& D = P->dev;
     const int d = P->d;
     const int sel_dt = CST_RUN + 3 * run, sel_nu = sel_dt + 1, sel_th = sel_dt + 2;
     void *Y = P->vec(V_Y), *K1 = P->vec(V_K1), *A = P->vec(V_A), *B = P->vec(V_B), *Cb = P->vec(V_C);
@@ -510,7 +577,7 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
                 a.b1 = P->sch.b[0];
                 a.b2 = P->sch.b[1];
             }
-            hipError_t err = launch_sweep(D, P->prec, ax, epi, a, s);
+            hipError_t err = run_sweep(P, ax, epi, a, s);
             if (err != hipSuccess) return err;
         }
         return hipSuccess;
@@ -520,14 +587,14 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
     st.X0 = Y;
     st.W = A;
     st.scale_sel = sel_dt;
-    if ((e = launch_stencil(D, P->prec, OP_F_PAYOFF, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+    if ((e = run_stencil(P, OP_F_PAYOFF, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     if ((e = chain(A, B, false)) != hipSuccess) return hip_fail(e, "sweep");
     // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d))
     st = StencilArgs{};
     st.X0 = B;
     st.W = A;
     st.scale_sel = sel_th;
-    if ((e = launch_stencil(D, P->prec, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+    if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     if ((e = chain(A, K1, false)) != hipSuccess) return hip_fail(e, "sweep");
     // ---- stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1
     st = StencilArgs{};
@@ -537,13 +604,13 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
     st.a = a21;
     st.q = q21;
     st.scale_sel = sel_dt;
-    if ((e = launch_stencil(D, P->prec, OP_STAGE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+    if ((e = run_stencil(P, OP_STAGE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     if ((e = chain(A, B, false)) != hipSuccess) return hip_fail(e, "sweep");
     st = StencilArgs{};
     st.X0 = B;
     st.W = A;
     st.scale_sel = sel_th;
-    if ((e = launch_stencil(D, P->prec, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+    if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     // second chain of stage 2 ends in Y += b1 K1 + b2 K2
     if (d == 1) return fail(AMF_E_UNSUPPORTED, "d = 1");
     if ((e = chain(A, B, true)) != hipSuccess) return hip_fail(e, "sweep");
@@ -558,7 +625,7 @@ amf_status amf_init(amf_plan* P, void* stream)
 {
     amf_status st = check_bound(P);
     if (st) return st;
-    hipError_t e = launch_init(P->dev, P->prec, P->vec(V_Y), (hipStream_t)stream);
+    hipError_t e = run_init(P, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "init");
     P->initialised = true;
     P->have_coarse = false;
@@ -585,9 +652,9 @@ amf_status amf_solve(amf_plan* P, void* stream)
     for (int i = 0; i < P->steps; ++i)
         if ((st = one_step(P, 0, s))) return st;
     if (P->richardson) {
-        hipError_t e = launch_unit_values(P->dev, P->prec, P->vec(V_Y), (double*)(P->ws + P->off_valsc), s);
+        hipError_t e = run_unit_values(P, (double*)(P->ws + P->off_valsc), s);
         if (e != hipSuccess) return hip_fail(e, "unit values");
-        if ((e = launch_init(P->dev, P->prec, P->vec(V_Y), s)) != hipSuccess) return hip_fail(e, "init");
+        if ((e = run_init(P, s)) != hipSuccess) return hip_fail(e, "init");
         for (int i = 0; i < 2 * P->steps; ++i)
             if ((st = one_step(P, 1, s))) return st;
         P->have_coarse = true;
@@ -600,7 +667,7 @@ amf_status amf_unit_values(amf_plan* P, double* d_values, void* stream)
     amf_status st = check_bound(P);
     if (st) return st;
     if (!d_values) return fail(AMF_E_INVALID, "null output");
-    hipError_t e = launch_unit_values(P->dev, P->prec, P->vec(V_Y), d_values, (hipStream_t)stream);
+    hipError_t e = run_unit_values(P, d_values, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "unit values");
     return AMF_OK;
 }
@@ -612,10 +679,12 @@ amf_status amf_combine(amf_plan* P, double* d_prices, void* stream)
     if (!d_prices) return fail(AMF_E_INVALID, "null output");
     hipStream_t s = (hipStream_t)stream;
     double* vals = (double*)(P->ws + P->off_vals);
-    hipError_t e = launch_unit_values(P->dev, P->prec, P->vec(V_Y), vals, s);
+    hipError_t e = run_unit_values(P, vals, s);
     if (e != hipSuccess) return hip_fail(e, "unit values");
     const double* coarse = (P->richardson && P->have_coarse) ? (const double*)(P->ws + P->off_valsc) : nullptr;
-    e = launch_combine(P->dev, (const double*)(P->ws + P->off_coef), vals, coarse, d_prices, s);
+    e = timed(P, AMF_K_COMBINE, 16.0 * P->n_units, s, [&] {
+        return launch_combine(P->dev, (const double*)(P->ws + P->off_coef), vals, coarse, d_prices, s);
+    });
     if (e != hipSuccess) return hip_fail(e, "combine");
     return AMF_OK;
 }
@@ -658,6 +727,40 @@ amf_status amf_axis_solve(amf_plan* P, int32_t axis, const void* d_in, void* d_o
     a.nudt_sel = CST_RUN + 1;
     hipError_t e = launch_sweep(P->dev, P->prec, axis, EPI_STORE, a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "sweep");
+    return AMF_OK;
+}
+
+amf_status amf_profile_begin(amf_plan* P)
+{
+    if (!P) return fail(AMF_E_INVALID, "null plan");
+    P->prof = true;
+    P->recs.clear();
+    P->pool_next = 0;
+    return AMF_OK;
+}
+
+amf_status amf_profile_end(amf_plan* P, amf_kernel_stat* stats)
+{
+    if (!P || !stats) return fail(AMF_E_INVALID, "null argument");
+    for (int k = 0; k < AMF_K_COUNT; ++k) {
+        stats[k] = amf_kernel_stat{};
+        stats[k].kernel = k;
+    }
+    P->prof = false;
+    if (!P->recs.empty()) {
+        hipError_t e = hipEventSynchronize(P->recs.back().b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    }
+    for (const auto& r : P->recs) {
+        float ms = 0.f;
+        hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+        stats[r.kclass].launches += 1;
+        stats[r.kclass].total_ms += ms;
+        stats[r.kclass].algo_bytes += r.bytes;
+    }
+    P->recs.clear();
+    P->pool_next = 0;
     return AMF_OK;
 }
 

@@ -160,6 +160,16 @@ class Plan:
         self.solve(stream)
         return self.combine(stream=stream)
 
+    def profile_begin(self):
+        L.check(L.lib().amf_profile_begin(self._h))
+
+    def profile_end(self) -> dict:
+        """Per kernel class: launches, summed event milliseconds and algorithmic bytes."""
+        arr = (L.AmfKernelStat * L.K_COUNT)()
+        L.check(L.lib().amf_profile_end(self._h, arr))
+        return {L.K_NAMES[s.kernel]: dict(launches=int(s.launches), ms=float(s.total_ms),
+                                          algo_bytes=float(s.algo_bytes)) for s in arr}
+
     def close(self):
         if getattr(self, "_h", None):
             L.lib().amf_plan_destroy(self._h)
