@@ -28,6 +28,68 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+COPY_BYTES = 2 << 30
+
+
+def kernel_class_of(name: str):
+    """Map a rocprofv3 kernel name to the library's kernel class (None for other kernels)."""
+    from paper_2408_00559_amd import _lib as L
+    if "k_sweep_strided<" in name:
+        up = ", 1," in name
+        lg = "true>" in name
+        return ("sweep_update" if up else "sweep_strided") + ("_long" if lg else "")
+    if "k_sweep_contig<" in name:
+        return "sweep_contig_long" if "true>" in name else "sweep_contig"
+    if "k_stencil<" in name:
+        op = name.split("k_stencil<", 1)[1].split(">", 1)[0].split(",")[-1].strip()
+        return {"0": "operator", "1": "operator", "2": "stage1", "3": "stage2", "4": "refine"}[op]
+    for k in ("k_node", "k_unit_values", "k_combine"):
+        if k in name:
+            return {"k_node": "init", "k_unit_values": "unit_values", "k_combine": "combine"}[k]
+    assert L.K_NAMES
+    return None
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, precision: str, out_path: str, command: str):
+    """Per kernel class: mean FETCH_SIZE and WRITE_SIZE per dispatch (KiB, from two rocprofv3 --pmc
+    runs), scaled by what the same counters read for the 2 GiB device-to-device copy."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        per, copies = {}, []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                name = r["Kernel_Name"]
+                if "copyBuffer" in name:
+                    copies.append(v)
+                k = kernel_class_of(name)
+                if k is not None:
+                    per.setdefault(k, []).append(v)
+        big = sorted(c for c in copies if c * 1024 > COPY_BYTES / 2)
+        scale = (COPY_BYTES / 1024.0) / big[len(big) // 2] if big else None
+        return {k: sum(v) / len(v) for k, v in per.items()}, scale, len(big)
+
+    fetch, fs, nf = load(fetch_dir, "FETCH_SIZE")
+    write, ws, nw = load(write_dir, "WRITE_SIZE")
+    rec = {}
+    for k in sorted(set(fetch) | set(write)):
+        if k in fetch and k in write and fs and ws:
+            rec[k] = {"fetch_KiB": fetch[k], "write_KiB": write[k],
+                      "bytes_per_launch": (fetch[k] * fs + write[k] * ws) * 1024.0}
+    old = json.load(open(out_path)) if os.path.exists(out_path) else {}
+    per_launch = old.get("per_launch", {}) if old.get("kernel_source_sha256_16") == kernel_hash() else {}
+    per_launch[precision] = rec
+    out = {"kernel_source_sha256_16": kernel_hash(), "copy_calibration": {
+        "bytes": COPY_BYTES, "fetch_scale": fs, "write_scale": ws, "copies_seen": [nf, nw]},
+        "command": command, "per_launch": per_launch}
+    json.dump(out, open(out_path, "w"), indent=1)
+    print(json.dumps(out))
+
+
 def traffic_for(kernel: str, precision: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on the
     current kernel source; else None."""
@@ -60,9 +122,11 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9
 
 
-def run_form(torch, Plan, w, precision, steps, warmup):
+def run_form(torch, Plan, w, precision, steps, warmup, tune=True):
+    from paper_2408_00559_amd import autotune
     plan = Plan(w["problems"], w["grid"], w["steps"], precision=precision, device="cuda:0")
-    prices = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    tuned = autotune.tune(plan, steps=2, reps=1) if tune else None
+    prices = torch.empty(len(w["problems"]), dtype=torch.float64, device="cuda:0")
     for _ in range(warmup):
         plan.solve()
         plan.combine(prices)
@@ -78,13 +142,15 @@ def run_form(torch, Plan, w, precision, steps, warmup):
     kstats = plan.profile_end()
     sec = (t1 - t0) / steps
     su = plan.stage_updates
-    price = float(prices.item())
+    price = float(prices[0].item())
     # dominant kernel by summed event time
-    dom = max(("stencil", "sweep", "sweep_update"), key=lambda k: kstats[k]["ms"])
+    hot = [k for k in kstats if k not in ("init", "operator", "unit_values", "combine")]
+    dom = max(hot, key=lambda k: kstats[k]["ms"])
     ks = kstats[dom]
     achieved = ks["algo_bytes"] / (ks["ms"] * 1e-3) / 1e9 if ks["ms"] > 0 else 0.0
     launches = max(ks["launches"], 1)
-    roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+    from paper_2408_00559_amd import _lib as L
+    roof = {"kernel": dom, "kernel_symbol": L.K_SYMBOLS[dom], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dom, precision),
             "algo_bytes_per_launch": ks["algo_bytes"] / launches,
             "avg_launch_us": ks["ms"] * 1e3 / launches, "launches_per_solve": ks["launches"] / steps}
@@ -92,7 +158,9 @@ def run_form(torch, Plan, w, precision, steps, warmup):
                       "GBps": (v["algo_bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                   for k, v in kstats.items() if v["launches"]}
     out = dict(value=su / sec, sec_per_solve=sec, price=price, stage_updates=su, roofline=roof,
-               kernels=per_kernel, units=plan.n_units, inner_points=plan.inner_points)
+               kernels=per_kernel, units=plan.n_units, inner_points=plan.inner_points,
+               schedule=plan.schedule(), autotune=(None if tuned is None else
+                                                   {"trials": tuned.get("trials"), "cached": tuned.get("cached")}))
     del plan
     torch.cuda.empty_cache()
     return out
@@ -156,7 +224,16 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/hbm_traffic_ct4.json from two rocprofv3 --pmc runs")
+    ap.add_argument("--pmc-precision", default="fp64")
+    ap.add_argument("--pmc-command", default="")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_precision,
+                      os.path.join(ROOT, "profiles", "hbm_traffic_ct4.json"), args.pmc_command)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the component grids are independent until the final "
               "FP64 combination, and this build measures one GPU's share (see DESIGN.md for the "
@@ -170,8 +247,11 @@ def main():
 
     w = I.workload_ct4()
     copy_gbps = copy_bandwidth(torch)
-    f64 = run_form(torch, Plan, w, "fp64", args.steps, args.warmup)
+    f64 = None if args.no_fp64 else run_form(torch, Plan, w, "fp64", args.steps, args.warmup)
     f32 = None if args.no_fp32 else run_form(torch, Plan, w, "fp32", args.steps, args.warmup)
+    if f64 is None:            # profiling runs of the FP32 form alone
+        print(json.dumps({"fp32": f32}), flush=True)
+        return
     golden = json.load(open(GOLDEN)) if os.path.exists(GOLDEN) else None
     ref = golden["price"] if golden else None
     res = {
@@ -197,6 +277,8 @@ def main():
         "rel_err_vs_oracle": (abs(f64["price"] - ref) / abs(ref)) if ref else None,
         "roofline": f64["roofline"],
         "kernels": f64["kernels"],
+        "schedule": f64["schedule"],
+        "autotune": f64["autotune"],
         "copy_GBps": copy_gbps,
     }
     if f32 is not None:
@@ -205,7 +287,8 @@ def main():
                        "ms_per_step": f32["sec_per_solve"] * 1e3, "prices_per_s": 1.0 / f32["sec_per_solve"],
                        "price": f32["price"], "rel_err": abs(f32["price"] - base) / abs(base),
                        "rel_err_against": "oracle" if ref else "fp64 GPU",
-                       "roofline": f32["roofline"], "kernels": f32["kernels"]}
+                       "roofline": f32["roofline"], "kernels": f32["kernels"],
+                       "schedule": f32["schedule"], "autotune": f32["autotune"]}
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

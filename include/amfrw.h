@@ -101,8 +101,9 @@ typedef struct {
     int64_t inner_points;             /* sum over units of prod M_i                                */
     int64_t stage_updates_per_solve;  /* inner_points * stages * steps (x3 with Richardson)        */
     uint64_t workspace_bytes;
-    uint64_t state_offset;            /* byte offset of the state vector Y inside the workspace   */
-    uint64_t vector_bytes;            /* bytes of one grid vector (all units)                      */
+    uint64_t state_offset;            /* byte offset of the stored Y - g inside the workspace      */
+    uint64_t vector_bytes;            /* bytes of one grid vector: all units, each unit's offset   */
+                                      /* rounded up to 64 elements (padding is never read)         */
     int32_t d;
     int32_t precision;                /* amf_precision                                             */
     int32_t n_steps;
@@ -164,8 +165,10 @@ amf_status amf_unit_values(amf_plan* plan, double* d_values, void* stream);
  * as they are and are the caller's to detect. */
 amf_status amf_combine(amf_plan* plan, double* d_prices, void* stream);
 
-/* Device pointer of the plan's solution vector Y (inner-node layout above, plan precision). */
-amf_status amf_state_ptr(const amf_plan* plan, void** d_state);
+/* Copy the current solution Y (inner-node layout above, plan precision) to d_out (device, at least
+ * vector_bytes).  The plan stores Y - g internally, g the payoff, which vanishes on the lower
+ * faces; this call adds g back. */
+amf_status amf_state_read(amf_plan* plan, void* d_out, void* stream);
 
 /* Step-level entry points (parity testing of the individual steps).  d_in / d_out are grid vectors
  * in the inner-node layout and the plan precision, distinct from the workspace.
@@ -178,19 +181,42 @@ amf_status amf_apply_operator(amf_plan* plan, const void* d_in, void* d_out, int
                               double scale, void* stream);
 amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* d_out, void* stream);
 
+/* Launch schedule of a plan (tuning knobs; results do not depend on them beyond rounding order
+ * of independent per-node sums, which they leave unchanged).
+ *   stencil_nodes: consecutive axis-1 nodes evaluated per thread by the time-loop operator
+ *                  (1, 2 or 4; at most max_stencil_nodes = min(4, smallest M_1 of the plan)).
+ *   xcd_remap:     1 = assign each XCD a contiguous share of the blocks (its own L2), 0 = off.
+ * amf_schedule_set may be called at any time between enqueued calls; AMF_E_INVALID otherwise. */
+typedef struct {
+    uint32_t struct_size;
+    int32_t stencil_nodes;
+    int32_t xcd_remap;
+    int32_t max_stencil_nodes;   /* read-only: filled by amf_schedule_get */
+} amf_schedule;
+
+amf_status amf_schedule_get(const amf_plan* plan, amf_schedule* out);
+amf_status amf_schedule_set(amf_plan* plan, const amf_schedule* schedule);
+
 /* Per-kernel timing (measurement support).  Between amf_profile_begin and amf_profile_end every
  * kernel the plan launches is bracketed by two HIP events recorded on its launch stream.
  * amf_profile_end waits for the last event and returns, per kernel class, the launch count, the
  * summed event time and the summed algorithmic bytes (bytes the kernel must move at minimum:
  * every vector it reads or writes once, in the plan precision). */
 typedef enum {
-    AMF_K_INIT = 0,        /* payoff initialisation                                    */
-    AMF_K_STENCIL = 1,     /* Sketch-1 operator fused with a stage combination          */
-    AMF_K_SWEEP = 2,       /* directional tridiagonal solves                            */
-    AMF_K_SWEEP_UPDATE = 3,/* last solve of a step fused with Y += b1 K1 + b2 K2        */
-    AMF_K_UNIT_VALUES = 4, /* interpolation at x_eval                                   */
-    AMF_K_COMBINE = 5,     /* FP64 combination                                          */
-    AMF_K_COUNT = 6
+    AMF_K_INIT = 0,             /* payoff / zero fills                                        */
+    AMF_K_OPERATOR = 1,         /* Sketch-1 operator alone (F of the payoff; step-level API)  */
+    AMF_K_STAGE1 = 2,           /* first-stage operator dt (F0(W) + F(g))                     */
+    AMF_K_STAGE2 = 3,           /* second-stage operator dt (F0(W + a K1) + F(g)) + q K1      */
+    AMF_K_REFINE = 4,           /* refinement 2 K - K^(d) + theta dt F(K^(d))                 */
+    AMF_K_SWEEP_CONTIG = 5,     /* axis-1 solves, lines up to 16 points                       */
+    AMF_K_SWEEP_CONTIG_LONG = 6,/* axis-1 solves, longer lines (partitioned, PCR over lanes)  */
+    AMF_K_SWEEP_STRIDED = 7,    /* solves along axes 2..d, lines up to 16 points              */
+    AMF_K_SWEEP_STRIDED_LONG = 8, /* ... longer lines                                         */
+    AMF_K_SWEEP_UPDATE = 9,     /* last solve of a step fused with W += b1 K1 + b2 K2, short  */
+    AMF_K_SWEEP_UPDATE_LONG = 10, /* ... longer lines                                         */
+    AMF_K_UNIT_VALUES = 11,     /* interpolation at x_eval                                    */
+    AMF_K_COMBINE = 12,         /* FP64 combination                                           */
+    AMF_K_COUNT = 13
 } amf_kernel_class;
 
 typedef struct {

@@ -46,12 +46,28 @@ class AmfPlanInfo(C.Structure):
                 ("precision", C.c_int32), ("n_steps", C.c_int32), ("richardson", C.c_int32)]
 
 
+class AmfSchedule(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("stencil_nodes", C.c_int32), ("xcd_remap", C.c_int32),
+                ("max_stencil_nodes", C.c_int32)]
+
+
 class AmfKernelStat(C.Structure):
     _fields_ = [("kernel", C.c_int32), ("reserved", C.c_int32), ("launches", C.c_int64),
                 ("total_ms", C.c_double), ("algo_bytes", C.c_double)]
 
 
-K_NAMES = ["init", "stencil", "sweep", "sweep_update", "unit_values", "combine"]
+K_NAMES = ["init", "operator", "stage1", "stage2", "refine", "sweep_contig", "sweep_contig_long",
+           "sweep_strided", "sweep_strided_long", "sweep_update", "sweep_update_long", "unit_values",
+           "combine"]
+# device kernel symbol of each class (template arguments omitted)
+K_SYMBOLS = {"init": "k_node", "operator": "k_stencil<OP_F_PAYOFF>", "stage1": "k_stencil<OP_STAGE1>",
+             "stage2": "k_stencil<OP_STAGE2>", "refine": "k_stencil<OP_REFINE>",
+             "sweep_contig": "k_sweep_contig<false>", "sweep_contig_long": "k_sweep_contig<true>",
+             "sweep_strided": "k_sweep_strided<EPI_STORE, false>",
+             "sweep_strided_long": "k_sweep_strided<EPI_STORE, true>",
+             "sweep_update": "k_sweep_strided<EPI_UPDATE, false>",
+             "sweep_update_long": "k_sweep_strided<EPI_UPDATE, true>",
+             "unit_values": "k_unit_values", "combine": "k_combine"}
 K_COUNT = len(K_NAMES)
 
 
@@ -98,12 +114,16 @@ def lib():
         L.amf_unit_values.argtypes = [vp, vp, vp]
         L.amf_combine.restype = st
         L.amf_combine.argtypes = [vp, vp, vp]
-        L.amf_state_ptr.restype = st
-        L.amf_state_ptr.argtypes = [vp, C.POINTER(vp)]
+        L.amf_state_read.restype = st
+        L.amf_state_read.argtypes = [vp, vp, vp]
         L.amf_apply_operator.restype = st
         L.amf_apply_operator.argtypes = [vp, vp, vp, C.c_int32, C.c_double, vp]
         L.amf_axis_solve.restype = st
         L.amf_axis_solve.argtypes = [vp, C.c_int32, vp, vp, vp]
+        L.amf_schedule_get.restype = st
+        L.amf_schedule_get.argtypes = [vp, C.POINTER(AmfSchedule)]
+        L.amf_schedule_set.restype = st
+        L.amf_schedule_set.argtypes = [vp, C.POINTER(AmfSchedule)]
         L.amf_profile_begin.restype = st
         L.amf_profile_begin.argtypes = [vp]
         L.amf_profile_end.restype = st
@@ -121,5 +141,5 @@ def check(status: int):
 
 EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_plan_create",
             "amf_plan_info_get", "amf_unit_info", "amf_plan_bind", "amf_init", "amf_time_step",
-            "amf_solve", "amf_unit_values", "amf_combine", "amf_state_ptr", "amf_apply_operator",
-            "amf_axis_solve", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy"]
+            "amf_solve", "amf_unit_values", "amf_combine", "amf_state_read", "amf_apply_operator",
+            "amf_axis_solve", "amf_schedule_get", "amf_schedule_set", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy"]

@@ -33,7 +33,8 @@ constexpr int RHO_LD = AMF_MAX_D - 1;   // leading dimension of amf_problem::rho
 
 }  // namespace
 
-enum VecId { V_Y = 0, V_K1 = 1, V_A = 2, V_B = 3, V_C = 4, N_VEC = 5 };
+// Grid vectors: the solution W = Y - g, the first stage K1, two work vectors and F(g).
+enum VecId { V_W = 0, V_K1 = 1, V_A = 2, V_B = 3, V_G = 4, N_VEC = 5 };
 
 struct amf_plan {
     int d = 0, prec = 0, steps = 0, richardson = 0, n_probs = 0, n_units = 0;
@@ -42,14 +43,21 @@ struct amf_plan {
     std::vector<UnitDev> units;            // n_units + sentinel
     std::vector<double> coef;              // combination coefficient per unit
     std::vector<double> tabd;              // coefficient tables in FP64
+    std::vector<double> facd;              // Thomas factor tables in FP64 (run 0, then run 1)
+    int64_t fac_run = 0;                   // elements per run in facd
     std::vector<ProbDev> probdev;
     std::vector<int32_t> blk_unit;
+    std::vector<int32_t> blk_unit_r[3];    // node blocks of NODE_BLOCK * {1, 2, 4} nodes
+    int stencil_r = 1, min_m0 = 1, xcd = 1;
     std::vector<int32_t> ax_units[MAXD];
     std::vector<int64_t> ax_line_off[MAXD];
     std::vector<SweepBlk> ax_blk[MAXD];
-    int64_t total = 0;
+    double ax_short_frac[MAXD]{};          // share of inner points on lines up to 2^SHORT_LM
+    int64_t total = 0;                     // elements per grid vector (with alignment padding)
+    int64_t inner = 0;                     // inner points over all units
 
-    size_t off_vec[N_VEC]{}, off_units = 0, off_probs = 0, off_tab = 0, off_blk = 0;
+    size_t off_vec[N_VEC]{}, off_units = 0, off_probs = 0, off_tab = 0, off_fac = 0, off_blk = 0;
+    size_t off_blkr[3]{};
     size_t off_axu[MAXD]{}, off_axl[MAXD]{}, off_axb[MAXD]{};
     size_t off_coef = 0, off_vals = 0, off_valsc = 0, ws_bytes = 0;
     size_t elem = 8;
@@ -168,6 +176,28 @@ void append_axis_table(std::vector<double>& t, const amf_problem& p, int axis, i
     }
 }
 
+// Thomas factors of (I - nu dt A_axis) along one line (Lemma lema:ls) from the FP64 diagonal
+// weights delta_r = d_axis/h^2: appends inv_r = 1/pivot_r, a_r inv_r, c'_r (three blocks of M).
+void append_factors(std::vector<double>& f, const std::vector<double>& delta, double nudt)
+{
+    const int M = (int)delta.size();
+    const size_t b = f.size();
+    f.resize(b + 3 * (size_t)M);
+    double cprev = 0.0;
+    for (int r = 0; r < M; ++r) {
+        const double nd = nudt * delta[r];
+        const double bb = 1.0 + 2.0 * nd;
+        const double a = (r == 0) ? 0.0 : ((r == M - 1) ? -2.0 * nd : -nd);
+        const double c = (r == M - 1) ? 0.0 : -nd;
+        const double inv = 1.0 / (bb - a * cprev);
+        const double cp = c * inv;
+        f[b + r] = inv;
+        f[b + M + r] = a * inv;
+        f[b + 2 * M + r] = cp;
+        cprev = cp;
+    }
+}
+
 template <typename T>
 std::vector<T> cast_vec(const std::vector<double>& v)
 {
@@ -239,6 +269,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             s += row[i];
         }
         if (s > 30) return fail(AMF_E_INVALID, "full grid too large (sum of levels > 30)");
+        if (row[0] > 10) return fail(AMF_E_UNSUPPORTED, "axis-1 level above 10 is not built");
         glv.push_back(row);
         gcf.push_back(1.0);
     } else {
@@ -246,6 +277,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         if (grid->n < d - 1) return fail(AMF_E_INVALID, "n must be >= d-1");
         if (grid->psi + grid->n > 16 || d * grid->psi + grid->n > 30)
             return fail(AMF_E_INVALID, "combination level too large");
+        if (grid->psi + grid->n > 10) return fail(AMF_E_UNSUPPORTED, "axis-1 level above 10 is not built");
         enumerate_grids(d, grid->n, grid->psi, glv, gcf);
     }
 
@@ -269,6 +301,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->n_units = (int)nu64;
 
         // coefficient tables: per problem a constant block, then (axis, level) blocks
+        std::vector<double> facs[2];
         for (int p = 0; p < n_probs; ++p) {
             const amf_problem& pr = probs[p];
             ProbDev pd{};
@@ -309,37 +342,83 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                     }
                 }
             P->probdev.push_back(pd);
+            // Thomas factors per (strided axis, level, V level) in use, both runs
+            std::vector<std::vector<int64_t>> fac_of(d, std::vector<int64_t>(17 * 17, -1));
+            // FP64 weights delta_r = d_ax / h_ax^2 along a line (as the coefficient tables hold them)
+            auto delta_of = [&](int ax, int L, int LV, int jv, const std::vector<double>& t,
+                                const std::vector<double>& tv) {
+                const int M = 1 << L, MV = 1 << LV;
+                std::vector<double> dl(M);
+                for (int r = 0; r < M; ++r)
+                    dl[r] = (ax < d - 1) ? t[r] * tv[jv] : tv[MV] * tv[r];
+                return dl;
+            };
+            std::vector<int64_t> unit_fac((size_t)ng * d, 0);
+            for (int g = 0; g < ng; ++g)
+                for (int i = 1; i < d; ++i) {
+                    const int L = glv[g][i], LV = glv[g][d - 1];
+                    const int key = (i < d - 1) ? L * 17 + LV : L * 17 + L;
+                    if (fac_of[i][key] < 0) {
+                        fac_of[i][key] = (int64_t)facs[0].size();
+                        const int nlines = (i < d - 1) ? (1 << LV) : 1;
+                        std::vector<double> t, tv;
+                        append_axis_table(t, pr, i, L);
+                        append_axis_table(tv, pr, d - 1, LV);
+                        for (int run = 0; run < 2; ++run) {
+                            const double h = run == 0 ? pr.maturity / (double)n_steps : 0.5 * pr.maturity / (double)n_steps;
+                            for (int jv = 0; jv < nlines; ++jv)
+                                append_factors(facs[run], delta_of(i, L, LV, jv, t, tv), scheme->nu * h);
+                        }
+                    }
+                    unit_fac[(size_t)g * d + i] = fac_of[i][key];
+                }
             for (int g = 0; g < ng; ++g) {
                 UnitDev U{};
+                P->total = (P->total + UNIT_ALIGN - 1) / UNIT_ALIGN * UNIT_ALIGN;
                 U.off = P->total;
                 U.prob = p;
                 int ls = 0;
                 for (int i = 0; i < d; ++i) {
                     U.lv[i] = (int8_t)glv[g][i];
                     U.tab[i] = blk_of[i][glv[g][i]];
+                    if (unit_fac[(size_t)g * d + i] > INT32_MAX) throw std::bad_alloc();
+                    U.fac[i] = (int32_t)unit_fac[(size_t)g * d + i];
                     ls += glv[g][i];
                 }
                 U.lsum = ls;
                 P->units.push_back(U);
                 P->coef.push_back(gcf[g]);
                 P->total += (int64_t)1 << ls;
+                P->inner += (int64_t)1 << ls;
             }
         }
+        P->total = (P->total + UNIT_ALIGN - 1) / UNIT_ALIGN * UNIT_ALIGN;
         UnitDev sentinel{};
         sentinel.off = P->total;
         P->units.push_back(sentinel);
+        P->fac_run = (int64_t)facs[0].size();
+        P->facd = std::move(facs[0]);
+        P->facd.insert(P->facd.end(), facs[1].begin(), facs[1].end());
 
         // node blocks -> first unit
-        const int64_t nblk = (P->total + NODE_BLOCK - 1) / NODE_BLOCK;
-        P->blk_unit.resize(nblk);
-        {
+        auto block_table = [&](int64_t per, std::vector<int32_t>& tbl) {
+            const int64_t nb = (P->total + per - 1) / per;
+            tbl.resize(nb);
             int u = 0;
-            for (int64_t b = 0; b < nblk; ++b) {
-                const int64_t g0 = b * NODE_BLOCK;
+            for (int64_t b = 0; b < nb; ++b) {
+                const int64_t g0 = b * per;
                 while (g0 >= P->units[u + 1].off) ++u;
-                P->blk_unit[b] = u;
+                tbl[b] = u;
             }
-        }
+        };
+        block_table(NODE_BLOCK, P->blk_unit);
+        for (int k = 0; k < 3; ++k) block_table((int64_t)NODE_BLOCK << k, P->blk_unit_r[k]);
+        // time-loop operator: R consecutive axis-0 nodes per thread, R <= every unit's M_0
+        int min_m0 = 1 << 16;
+        for (int u = 0; u < P->n_units; ++u) min_m0 = std::min(min_m0, 1 << P->units[u].lv[0]);
+        P->min_m0 = min_m0;
+        const int rmax = precision == AMF_FP64 ? STENCIL_R_F64 : STENCIL_R_F32;
+        P->stencil_r = std::min(rmax, min_m0) >= 4 ? 4 : (std::min(rmax, min_m0) >= 2 ? 2 : 1);
         // per axis: units ordered by M_axis, line offsets, blocks that never mix line lengths
         for (int ax = 0; ax < d; ++ax) {
             std::vector<int32_t>& ord = P->ax_units[ax];
@@ -355,17 +434,23 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 const UnitDev& U = P->units[ord[k]];
                 lo[k + 1] = lo[k] + ((int64_t)1 << (U.lsum - U.lv[ax]));
             }
+            int64_t short_pts = 0;
+            for (int u = 0; u < P->n_units; ++u)
+                if (P->units[u].lv[ax] <= SHORT_LM) short_pts += (int64_t)1 << P->units[u].lsum;
+            P->ax_short_frac[ax] = P->inner > 0 ? (double)short_pts / (double)P->inner : 0.0;
             int k0 = 0;
             while (k0 < P->n_units) {
                 const int lm = P->units[ord[k0]].lv[ax];
                 int k1 = k0;
                 while (k1 < P->n_units && P->units[ord[k1]].lv[ax] == lm) ++k1;
                 int k = k0;
-                for (int64_t s = lo[k0]; s < lo[k1]; s += LINE_BLOCK) {
+                // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each
+                const int per = (ax == 0 && lm > CONTIG_REG_LM) ? LINE_BLOCK / ((1 << lm) / SEG) : LINE_BLOCK;
+                for (int64_t s = lo[k0]; s < lo[k1]; s += per) {
                     while (s >= lo[k + 1]) ++k;
                     SweepBlk B{};
                     B.line_start = s;
-                    B.line_end = std::min<int64_t>(s + LINE_BLOCK, lo[k1]);
+                    B.line_end = std::min<int64_t>(s + per, lo[k1]);
                     B.k_start = k;
                     B.lm = lm;
                     P->ax_blk[ax].push_back(B);
@@ -389,7 +474,9 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->off_units = take(P->units.size() * sizeof(UnitDev));
         P->off_probs = take(P->probdev.size() * sizeof(ProbDev));
         P->off_tab = take(P->tabd.size() * P->elem);
+        P->off_fac = take(P->facd.size() * P->elem);
         P->off_blk = take(P->blk_unit.size() * sizeof(int32_t));
+        for (int k = 0; k < 3; ++k) P->off_blkr[k] = take(P->blk_unit_r[k].size() * sizeof(int32_t));
         for (int ax = 0; ax < d; ++ax) {
             P->off_axu[ax] = take(P->ax_units[ax].size() * sizeof(int32_t));
             P->off_axl[ax] = take(P->ax_line_off[ax].size() * sizeof(int64_t));
@@ -412,10 +499,10 @@ amf_status amf_plan_info_get(const amf_plan* P, amf_plan_info* out)
     if (!P || !out) return fail(AMF_E_INVALID, "null argument");
     out->n_problems = P->n_probs;
     out->n_units = P->n_units;
-    out->inner_points = P->total;
-    out->stage_updates_per_solve = P->total * (int64_t)P->sch.stages * P->steps * (P->richardson ? 3 : 1);
+    out->inner_points = P->inner;
+    out->stage_updates_per_solve = P->inner * (int64_t)P->sch.stages * P->steps * (P->richardson ? 3 : 1);
     out->workspace_bytes = P->ws_bytes;
-    out->state_offset = P->off_vec[V_Y];
+    out->state_offset = P->off_vec[V_W];
     out->vector_bytes = (uint64_t)P->total * P->elem;
     out->d = P->d;
     out->precision = P->prec;
@@ -459,7 +546,16 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
         tf = cast_vec<float>(P->tabd);
         if ((st = upload(P->ws + P->off_tab, tf.data(), tf.size() * 4, s))) return st;
     }
+    std::vector<float> ff;
+    if (P->prec == AMF_FP64) {
+        if ((st = upload(P->ws + P->off_fac, P->facd.data(), P->facd.size() * 8, s))) return st;
+    } else {
+        ff = cast_vec<float>(P->facd);
+        if ((st = upload(P->ws + P->off_fac, ff.data(), ff.size() * 4, s))) return st;
+    }
     if ((st = upload(P->ws + P->off_blk, P->blk_unit.data(), P->blk_unit.size() * 4, s))) return st;
+    for (int k = 0; k < 3; ++k)
+        if ((st = upload(P->ws + P->off_blkr[k], P->blk_unit_r[k].data(), P->blk_unit_r[k].size() * 4, s))) return st;
     for (int ax = 0; ax < P->d; ++ax) {
         if ((st = upload(P->ws + P->off_axu[ax], P->ax_units[ax].data(), P->ax_units[ax].size() * 4, s))) return st;
         if ((st = upload(P->ws + P->off_axl[ax], P->ax_line_off[ax].data(), P->ax_line_off[ax].size() * 8, s))) return st;
@@ -478,13 +574,24 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
     D.units = (const UnitDev*)(P->ws + P->off_units);
     D.probs = (const ProbDev*)(P->ws + P->off_probs);
     D.tab = P->ws + P->off_tab;
+    D.fac = P->ws + P->off_fac;
+    D.fac_run_stride = P->fac_run;
     D.blk_unit = (const int32_t*)(P->ws + P->off_blk);
     D.n_node_blocks = (int64_t)P->blk_unit.size();
+    D.stencil_r = P->stencil_r;
+    D.xcd = P->xcd;
+    for (int k = 0; k < 3; ++k) {
+        D.blk_unit_r[k] = (const int32_t*)(P->ws + P->off_blkr[k]);
+        D.n_blocks_r[k] = (int64_t)P->blk_unit_r[k].size();
+    }
     for (int ax = 0; ax < P->d; ++ax) {
         D.ax_units[ax] = (const int32_t*)(P->ws + P->off_axu[ax]);
         D.ax_line_off[ax] = (const int64_t*)(P->ws + P->off_axl[ax]);
         D.ax_blk[ax] = (const SweepBlk*)(P->ws + P->off_axb[ax]);
         D.ax_nblk[ax] = (int64_t)P->ax_blk[ax].size();
+        int64_t ns = 0;
+        while (ns < D.ax_nblk[ax] && P->ax_blk[ax][ns].lm <= SHORT_LM) ++ns;
+        D.ax_nblk_short[ax] = ns;
     }
     P->bound = true;
     return AMF_OK;
@@ -528,28 +635,51 @@ hipError_t timed(amf_plan* P, int kclass, double bytes, hipStream_t s, Fn&& fn)
 
 hipError_t run_stencil(amf_plan* P, int op, const StencilArgs& a, hipStream_t s)
 {
-    const double nv = (op == OP_F_PAYOFF || op == OP_F_ZERO) ? 2.0 : 3.0;
-    return timed(P, AMF_K_STENCIL, nv * P->vbytes(), s,
-                 [&] { return launch_stencil(P->dev, P->prec, op, a, s); });
+    // vectors read or written once: F only 2; stage 1 (W, F(g), out) 3; stage 2 (W, K1, F(g), out)
+    // 4; refinement (K^(d), K^(0) in and out) 3
+    const double nv = (op == OP_F_PAYOFF || op == OP_F_ZERO) ? 2.0 : (op == OP_STAGE2 ? 4.0 : 3.0);
+    const int kc = op == OP_STAGE1 ? AMF_K_STAGE1 : op == OP_STAGE2 ? AMF_K_STAGE2
+                 : op == OP_REFINE ? AMF_K_REFINE : AMF_K_OPERATOR;
+    return timed(P, kc, nv * P->vbytes(), s, [&] { return launch_stencil(P->dev, P->prec, op, a, s); });
 }
 
+// Both launches (short and long lines) of one directional solve.  Algorithmic bytes: the part's
+// share of the vector read and written once (four vectors for the update form).
 hipError_t run_sweep(amf_plan* P, int axis, int epi, const SweepArgs& a, hipStream_t s)
 {
     const bool up = epi == EPI_UPDATE;
-    return timed(P, up ? AMF_K_SWEEP_UPDATE : AMF_K_SWEEP, (up ? 4.0 : 2.0) * P->vbytes(), s,
-                 [&] { return launch_sweep(P->dev, P->prec, axis, epi, a, s); });
+    for (int part = 0; part < 2; ++part) {
+        const double share = part == 0 ? P->ax_short_frac[axis] : 1.0 - P->ax_short_frac[axis];
+        if (share <= 0.0) continue;
+        const int kc = axis == 0 ? (part ? AMF_K_SWEEP_CONTIG_LONG : AMF_K_SWEEP_CONTIG)
+                     : up ? (part ? AMF_K_SWEEP_UPDATE_LONG : AMF_K_SWEEP_UPDATE)
+                          : (part ? AMF_K_SWEEP_STRIDED_LONG : AMF_K_SWEEP_STRIDED);
+        const double bytes = (up ? 4.0 : 2.0) * share * (double)P->inner * (double)P->elem;
+        hipError_t e = timed(P, kc, bytes, s, [&] { return launch_sweep(P->dev, P->prec, axis, epi, part, a, s); });
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
+// Initial data (dis0) in the W = Y - g form: F(g) once (payoff on the lower faces), then W = 0.
 hipError_t run_init(amf_plan* P, hipStream_t s)
 {
-    return timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_init(P->dev, P->prec, P->vec(V_Y), s); });
+    hipError_t e = timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_payoff(P->dev, P->prec, P->vec(V_A), s); });
+    if (e != hipSuccess) return e;
+    StencilArgs a{};
+    a.X0 = P->vec(V_A);
+    a.W = P->vec(V_G);
+    a.scale = 1.0;
+    a.scale_sel = -1;
+    if ((e = run_stencil(P, OP_F_PAYOFF, a, s)) != hipSuccess) return e;
+    return timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_fill_zero(P->dev, P->prec, P->vec(V_W), s); });
 }
 
 hipError_t run_unit_values(amf_plan* P, double* vals, hipStream_t s)
 {
     const double b = (double)P->n_units * (double)(1 << P->d) * (double)P->elem + 8.0 * P->n_units;
     return timed(P, AMF_K_UNIT_VALUES, b, s,
-                 [&] { return launch_unit_values(P->dev, P->prec, P->vec(V_Y), vals, s); });
+                 [&] { return launch_unit_values(P->dev, P->prec, P->vec(V_W), vals, s); });
 }
 
 // One AMFR-W step (eq amfrw) of the 2-stage scheme on every unit.  run selects dt (0: coarse,
@@ -557,22 +687,21 @@ hipError_t run_unit_values(amf_plan* P, double* vals, hipStream_t s)
 amf_status one_step(amf_plan* P, int run, hipStream_t s)
 {
     const int d = P->d;
-    const int sel_dt = CST_RUN + 3 * run, sel_nu = sel_dt + 1, sel_th = sel_dt + 2;
-    void *Y = P->vec(V_Y), *K1 = P->vec(V_K1), *A = P->vec(V_A), *B = P->vec(V_B), *Cb = P->vec(V_C);
+    const int sel_dt = CST_RUN + 3 * run, sel_th = sel_dt + 2;
+    void *Wv = P->vec(V_W), *K1 = P->vec(V_K1), *A = P->vec(V_A), *B = P->vec(V_B), *G = P->vec(V_G);
     const double a21 = P->sch.a[1 * AMF_MAX_STAGES + 0], q21 = P->sch.q[1 * AMF_MAX_STAGES + 0];
     hipError_t e;
+    // (I - nu dt A_1) .. (I - nu dt A_d) applied in axis order; the first solve is out of place
     auto chain = [&](const void* in, void* dst, bool last_update) -> hipError_t {
-        // (I - nu dt A_1)..(I - nu dt A_d) applied in axis order; first sweep out of place
         for (int ax = 0; ax < d; ++ax) {
             SweepArgs a{};
             a.in = ax == 0 ? in : dst;
             a.out = dst;
-            a.cbuf = Cb;
-            a.nudt_sel = sel_nu;
+            a.run = run;
             int epi = EPI_STORE;
             if (last_update && ax == d - 1) {
                 epi = EPI_UPDATE;
-                a.out = Y;
+                a.out = Wv;
                 a.K1 = K1;
                 a.b1 = P->sch.b[0];
                 a.b2 = P->sch.b[1];
@@ -582,12 +711,13 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
         }
         return hipSuccess;
     };
-    // ---- stage 1: K^(0) = dt F(Y)
+    // ---- stage 1: K^(0) = dt F(Y) = dt (F0(W) + F(g))
     StencilArgs st{};
-    st.X0 = Y;
+    st.X0 = Wv;
+    st.cG = G;
     st.W = A;
     st.scale_sel = sel_dt;
-    if ((e = run_stencil(P, OP_F_PAYOFF, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+    if ((e = run_stencil(P, OP_STAGE1, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     if ((e = chain(A, B, false)) != hipSuccess) return hip_fail(e, "sweep");
     // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d))
     st = StencilArgs{};
@@ -598,21 +728,21 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
     if ((e = chain(A, K1, false)) != hipSuccess) return hip_fail(e, "sweep");
     // ---- stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1
     st = StencilArgs{};
-    st.X0 = Y;
+    st.X0 = Wv;
     st.X1 = K1;
+    st.cG = G;
     st.W = A;
     st.a = a21;
     st.q = q21;
     st.scale_sel = sel_dt;
-    if ((e = run_stencil(P, OP_STAGE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+    if ((e = run_stencil(P, OP_STAGE2, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     if ((e = chain(A, B, false)) != hipSuccess) return hip_fail(e, "sweep");
     st = StencilArgs{};
     st.X0 = B;
     st.W = A;
     st.scale_sel = sel_th;
     if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    // second chain of stage 2 ends in Y += b1 K1 + b2 K2
-    if (d == 1) return fail(AMF_E_UNSUPPORTED, "d = 1");
+    // second chain of stage 2 ends in W += b1 K1 + b2 K2
     if ((e = chain(A, B, true)) != hipSuccess) return hip_fail(e, "sweep");
     return AMF_OK;
 }
@@ -654,7 +784,8 @@ amf_status amf_solve(amf_plan* P, void* stream)
     if (P->richardson) {
         hipError_t e = run_unit_values(P, (double*)(P->ws + P->off_valsc), s);
         if (e != hipSuccess) return hip_fail(e, "unit values");
-        if ((e = run_init(P, s)) != hipSuccess) return hip_fail(e, "init");
+        if ((e = timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_fill_zero(P->dev, P->prec, P->vec(V_W), s); })) != hipSuccess)
+            return hip_fail(e, "init");
         for (int i = 0; i < 2 * P->steps; ++i)
             if ((st = one_step(P, 1, s))) return st;
         P->have_coarse = true;
@@ -689,12 +820,13 @@ amf_status amf_combine(amf_plan* P, double* d_prices, void* stream)
     return AMF_OK;
 }
 
-amf_status amf_state_ptr(const amf_plan* P, void** d_state)
+amf_status amf_state_read(amf_plan* P, void* d_out, void* stream)
 {
     amf_status st = check_bound(P);
     if (st) return st;
-    if (!d_state) return fail(AMF_E_INVALID, "null output");
-    *d_state = P->vec(V_Y);
+    if (!d_out) return fail(AMF_E_INVALID, "null output");
+    hipError_t e = launch_state_read(P->dev, P->prec, P->vec(V_W), d_out, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "state read");
     return AMF_OK;
 }
 
@@ -723,10 +855,35 @@ amf_status amf_axis_solve(amf_plan* P, int32_t axis, const void* d_in, void* d_o
     SweepArgs a{};
     a.in = d_in;
     a.out = d_out;
-    a.cbuf = P->vec(V_C);
-    a.nudt_sel = CST_RUN + 1;
-    hipError_t e = launch_sweep(P->dev, P->prec, axis, EPI_STORE, a, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "sweep");
+    a.run = 0;
+    for (int part = 0; part < 2; ++part) {
+        hipError_t e = launch_sweep(P->dev, P->prec, axis, EPI_STORE, part, a, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "sweep");
+    }
+    return AMF_OK;
+}
+
+amf_status amf_schedule_get(const amf_plan* P, amf_schedule* out)
+{
+    if (!P || !out) return fail(AMF_E_INVALID, "null argument");
+    out->struct_size = sizeof(amf_schedule);
+    out->stencil_nodes = P->stencil_r;
+    out->xcd_remap = P->xcd;
+    out->max_stencil_nodes = std::min(4, P->min_m0);
+    return AMF_OK;
+}
+
+amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
+{
+    if (!P || !sc || sc->struct_size != sizeof(amf_schedule)) return fail(AMF_E_INVALID, "bad amf_schedule");
+    const int r = sc->stencil_nodes;
+    if (r != 1 && r != 2 && r != 4) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2 or 4");
+    if (r > P->min_m0) return fail(AMF_E_INVALID, "stencil_nodes exceeds the smallest axis-1 line");
+    if (sc->xcd_remap != 0 && sc->xcd_remap != 1) return fail(AMF_E_INVALID, "xcd_remap must be 0 or 1");
+    P->stencil_r = r;
+    P->xcd = sc->xcd_remap;
+    P->dev.stencil_r = r;
+    P->dev.xcd = P->xcd;
     return AMF_OK;
 }
 

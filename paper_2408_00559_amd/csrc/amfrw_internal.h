@@ -8,9 +8,24 @@ namespace amf {
 
 constexpr int MAXD = 6;            // kernels are instantiated for d = 2..6
 constexpr int NODE_BLOCK = 256;    // threads per block of the per-node kernels
-constexpr int LINE_BLOCK = 256;    // lines per block of the sweep kernels
-constexpr int REG_LM_F64 = 5;      // lines up to 2^5 points keep their Thomas factors in VGPRs (FP64)
-constexpr int REG_LM_F32 = 6;      // ... up to 2^6 points in FP32
+constexpr int LINE_BLOCK = 256;    // threads per block of the sweep kernels
+constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
+constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
+// Longest strided line kept whole in VGPRs by one thread (log2); longer lines stream through
+// memory in chunks of CHUNK rows.
+constexpr int REG_LM = 5;
+constexpr int CHUNK = 16;
+constexpr int NXCD = 8;
+// Default nodes per thread of the time-loop operator, by precision (limited by each unit's M_0);
+// a plan's schedule may override it.
+constexpr int STENCIL_R_F64 = 4;
+constexpr int STENCIL_R_F32 = 4;            // MI355X: 8 XCDs, each with its own L2
+// Contiguous (axis 0) lines up to 2^CONTIG_REG_LM are solved by one thread; longer ones by SEG-row
+// segments on M/SEG cooperating lanes.
+constexpr int CONTIG_REG_LM = 4;
+// Sweep launches are split by line length: classes up to 2^SHORT_LM and longer ones, so that
+// short lines are not held to the register allocation of the long-line code.
+constexpr int SHORT_LM = 4;
 
 // Per-problem constants in the plan precision, at ProbDev::cst inside the table array.
 enum CstIndex : int {
@@ -22,12 +37,13 @@ enum CstIndex : int {
 
 // One unit = one (problem, component grid) pair.  Inner nodes only, axis 0 fastest.
 struct alignas(16) UnitDev {
-    int64_t off;          // element offset of the unit in every grid vector
+    int64_t off;          // element offset of the unit in every grid vector (multiple of UNIT_ALIGN)
     int32_t prob;         // problem index
     int32_t lsum;         // sum of levels = log2(#inner points)
     int8_t lv[MAXD];      // log2 M_i
     int8_t pad_[2];
-    int32_t tab[MAXD];    // offset (elements) of the coefficient block of (prob, axis i, lv_i)
+    int32_t tab[MAXD];    // offset of the coefficient block of (prob, axis i, lv_i) in the tables
+    int32_t fac[MAXD];    // offset of the Thomas factor block of (prob, axis i, lv_i, lv_V), run 0
 };
 
 // Per-problem data in FP64 (payoff, interpolation, combination).
@@ -57,31 +73,41 @@ struct DevPlan {
     int d;
     int n_units;
     int n_probs;
-    int64_t total;               // inner points over all units
+    int64_t total;               // elements per grid vector (inner points + alignment padding)
     const UnitDev* units;        // n_units + 1 (sentinel off = total)
     const ProbDev* probs;
     const void* tab;             // coefficient tables, plan precision
+    const void* fac;             // Thomas factor tables (inv, a*inv, c'), plan precision
+    int64_t fac_run_stride;      // elements between the run-0 and run-1 factor tables
     const int32_t* blk_unit;     // per node block: first unit
     int64_t n_node_blocks;
+    int stencil_r;               // nodes per thread of the time-loop operator (1, 2 or 4)
+    int xcd;                     // 1: XCD-aware block remapping
+    const int32_t* blk_unit_r[3];   // per block of NODE_BLOCK * R nodes (R = 1, 2, 4): first unit
+    int64_t n_blocks_r[3];
     const int32_t* ax_units[MAXD];     // per axis: units ordered by M_axis
     const int64_t* ax_line_off[MAXD];  // per axis: first line of each listed unit (+ sentinel)
     const SweepBlk* ax_blk[MAXD];
     int64_t ax_nblk[MAXD];
+    int64_t ax_nblk_short[MAXD];       // leading blocks with lm <= SHORT_LM
 };
 
-// Stencil operation selector.
+// Stencil operation selector.  Solution vectors are stored as W = Y - g (zero on every lower face);
+// cG = F(g) is computed once per solve with the payoff on the lower faces.
 enum StencilOp : int {
     OP_F_PAYOFF = 0,   // W = s F(X0), lower faces = payoff
     OP_F_ZERO = 1,     // W = s F(X0), lower faces = 0
-    OP_STAGE = 2,      // W = s F(X0 + a X1) + q X1, lower faces = payoff
-    OP_REFINE = 3      // W = 2 W - X0 + s F(X0), lower faces = 0
+    OP_STAGE1 = 2,     // W = s (F(X0) + cG)                  (first stage, X0 = W_n)
+    OP_STAGE2 = 3,     // W = s (F(X0 + a X1) + cG) + q X1    (second stage, X1 = K_1)
+    OP_REFINE = 4      // W = 2 W - X0 + s F(X0)              (refinement of eq amfrw)
 };
 
 struct StencilArgs {
     const void* X0;
     const void* X1;
+    const void* cG;
     void* W;
-    double a, q;          // OP_STAGE coefficients
+    double a, q;          // OP_STAGE2 coefficients
     double scale;         // explicit scale when scale_sel < 0
     int scale_sel;        // else index into the per-problem constant block
 };
@@ -90,19 +116,21 @@ enum SweepEpi : int { EPI_STORE = 0, EPI_UPDATE = 1 };
 
 struct SweepArgs {
     const void* in;
-    void* out;            // EPI_STORE target; EPI_UPDATE: the solution Y (updated in place)
-    void* cbuf;           // scratch vector for long lines
+    void* out;            // EPI_STORE target; EPI_UPDATE: the solution W (updated in place)
     const void* K1;       // EPI_UPDATE: first stage
-    double b1, b2;        // EPI_UPDATE: Y += b1 K1 + b2 x
-    int nudt_sel;         // index into the per-problem constant block
+    double b1, b2;        // EPI_UPDATE: W += b1 K1 + b2 x
+    int run;              // 0 coarse, 1 fine (Richardson)
 };
 
 // Kernel launchers (amfrw_kernels.hip).  Return hipSuccess or the launch error.
-hipError_t launch_init(const DevPlan& P, int prec, void* Y, hipStream_t s);
+hipError_t launch_payoff(const DevPlan& P, int prec, void* Y, hipStream_t s);
+hipError_t launch_fill_zero(const DevPlan& P, int prec, void* Y, hipStream_t s);
+hipError_t launch_state_read(const DevPlan& P, int prec, const void* W, void* Y, hipStream_t s);
 hipError_t launch_stencil(const DevPlan& P, int prec, int op, const StencilArgs& a, hipStream_t s);
-hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, const SweepArgs& a,
+// part 0: lines up to 2^SHORT_LM points; part 1: longer lines.
+hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part, const SweepArgs& a,
                         hipStream_t s);
-hipError_t launch_unit_values(const DevPlan& P, int prec, const void* Y, double* vals,
+hipError_t launch_unit_values(const DevPlan& P, int prec, const void* W, double* vals,
                               hipStream_t s);
 hipError_t launch_combine(const DevPlan& P, const double* coef, const double* vals,
                           const double* vals_coarse, double* prices, hipStream_t s);

@@ -2,9 +2,11 @@
 // the AMFR-W stage combinations, the directional tridiagonal solves of Lemma lema:ls, tensor-product
 // interpolation and the FP64 combination of component-grid values.
 //
-// Layout: every grid vector stores the inner nodes of all units back to back; inside a unit axis 0
-// is fastest and M_i = 2^lv_i, so index decoding is shifts and masks.  Lower-face (Outer) values are
-// never stored: they are the payoff for solution vectors and 0 for increments.
+// Layout: every grid vector stores the inner nodes of all units back to back (unit offsets aligned
+// to 64 elements); inside a unit axis 0 is fastest and M_i = 2^lv_i, so index decoding is shifts and
+// masks.  Solution vectors hold W = Y - g, which vanishes on every lower (Dirichlet) face, so the
+// time loop never evaluates the payoff: F(Y) = F0(W) + F(g) with F0 the zero-face operator and F(g)
+// computed once per solve.
 #include "amfrw_internal.h"
 
 namespace amf {
@@ -25,6 +27,15 @@ __device__ __forceinline__ double payoff_at(const ProbDev& P, int nr, const doub
     return sum > 0.0 ? sum : 0.0;
 }
 
+// Blocks are dealt round-robin to the XCDs; remap so that each XCD works on one contiguous eighth
+// of the block range, keeping stencil halos and neighbouring lines in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int on)
+{
+    if (!on) return b;
+    const int64_t x = b % NXCD, i = b / NXCD, q = nb / NXCD, r = nb % NXCD;
+    return x * q + (x < r ? x : r) + i;
+}
+
 __device__ __forceinline__ int find_unit(const UnitDev* units, int u, int64_t g)
 {
     while (g >= units[u + 1].off) ++u;
@@ -32,26 +43,37 @@ __device__ __forceinline__ int find_unit(const UnitDev* units, int u, int64_t g)
 }
 
 // ------------------------------------------------------------------------------------------------
-// Initial data (dis0): Y = g at every inner node.
-template <typename T, int D>
-__global__ __launch_bounds__(NODE_BLOCK) void k_init(DevPlan P, T* Y)
+// Per-node kernels: payoff g at every inner node, W = 0, and Y = W + g for read-back.
+template <typename T, int D, int MODE>   // MODE 0: Y = g;  1: Y = 0;  2: Y = W + g
+__global__ __launch_bounds__(NODE_BLOCK) void k_node(DevPlan P, const T* Win, T* Y)
 {
-    const int64_t g = (int64_t)blockIdx.x * NODE_BLOCK + threadIdx.x;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd);
+    const int64_t g = lb * NODE_BLOCK + threadIdx.x;
     if (g >= P.total) return;
-    const int u = find_unit(P.units, P.blk_unit[blockIdx.x], g);
+    const int u = find_unit(P.units, P.blk_unit[lb], g);
     const UnitDev U = P.units[u];
-    const ProbDev& PR = P.probs[U.prob];
     const int64_t loc = g - U.off;
-    double x[MAXD];
-    int sh = 0;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const int M = 1 << U.lv[i];
-        const int j = (int)((loc >> sh) & (M - 1)) + 1;
-        x[i] = (double)j * (PR.xmax[i] / (double)M);
-        sh += U.lv[i];
+    if (loc >= ((int64_t)1 << U.lsum)) {   // alignment padding
+        Y[g] = T(0);
+        return;
     }
-    Y[g] = (T)payoff_at(PR, D - 1, x);
+    if constexpr (MODE == 1) {
+        Y[g] = T(0);
+    } else {
+        const ProbDev& PR = P.probs[U.prob];
+        double x[MAXD];
+        int sh = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int M = 1 << U.lv[i];
+            const int j = (int)((loc >> sh) & (M - 1)) + 1;
+            x[i] = (double)j * (PR.xmax[i] / (double)M);
+            sh += U.lv[i];
+        }
+        const double gv = payoff_at(PR, D - 1, x);
+        if constexpr (MODE == 0) Y[g] = (T)gv;
+        else Y[g] = (T)((double)Win[g] + gv);
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -68,14 +90,16 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_init(DevPlan P, T* Y)
 template <typename T, int D, int OP>
 __global__ __launch_bounds__(NODE_BLOCK) void k_stencil(DevPlan P, StencilArgs A)
 {
-    const int64_t g = (int64_t)blockIdx.x * NODE_BLOCK + threadIdx.x;
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd);
+    const int64_t g = lb * NODE_BLOCK + threadIdx.x;
     if (g >= P.total) return;
-    const int u = find_unit(P.units, P.blk_unit[blockIdx.x], g);
+    const int u = find_unit(P.units, P.blk_unit[lb], g);
     const UnitDev U = P.units[u];
+    const int64_t loc = g - U.off;
+    if (loc >= ((int64_t)1 << U.lsum)) return;   // alignment padding
     const ProbDev& PR = P.probs[U.prob];
     const T* tab = (const T*)P.tab;
     const T* cst = tab + PR.cst;
-    const int64_t loc = g - U.off;
 
     int j[D], M[D];
     int64_t E[D];
@@ -93,13 +117,12 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil(DevPlan P, StencilArgs A
     const T* X1 = (const T*)A.X1;
     const T av = (T)A.a;
     auto X = [&](int64_t idx) -> T {
-        if constexpr (OP == OP_STAGE) return X0[idx] + av * X1[idx];
+        if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
         else return X0[idx];
     };
-    constexpr bool payface = (OP == OP_F_PAYOFF || OP == OP_STAGE);
     // value at j + si e_i + sk e_k when that node lies on a lower face
     auto face = [&](int i, int si, int k, int sk) -> T {
-        if constexpr (!payface) {
+        if constexpr (OP != OP_F_PAYOFF) {
             return T(0);
         } else {
             double x[MAXD];
@@ -159,29 +182,226 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil(DevPlan P, StencilArgs A
     const T F = vsq * acc;
     const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
     T* W = (T*)A.W;
+    const T* cG = (const T*)A.cG;
     if constexpr (OP == OP_F_PAYOFF || OP == OP_F_ZERO) {
         W[g] = sc * F;
-    } else if constexpr (OP == OP_STAGE) {
-        W[g] = sc * F + (T)A.q * X1[g];
+    } else if constexpr (OP == OP_STAGE1) {
+        W[g] = sc * (F + cG[g]);
+    } else if constexpr (OP == OP_STAGE2) {
+        W[g] = sc * (F + cG[g]) + (T)A.q * X1[g];
     } else {
         W[g] = T(2) * W[g] - X0[g] + sc * F;
     }
 }
 
 // ------------------------------------------------------------------------------------------------
-// Directional solve (I - nu dt A_i) x = G along one line (Lemma lema:ls): rows r = 0..M-1 with
-// delta_r = d_i / h_i^2, diagonal 1 + 2 nu dt delta_r, super-diagonal -nu dt delta_r (none in the
-// last row), sub-diagonal -nu dt delta_r (none in the first row, doubled in the last row: Neumann).
-struct LineGeom {
-    int64_t base;     // element index of row 0
-    int64_t stride;   // E_axis
-    const void* dtab; // rate axis: tdiff block; V axis: vsq block
-    double cmul;      // rate axis: vsq(j_V); V axis: tdiff_V
+// The same operator for the time loop (zero lower faces: W, K1 and the increments all vanish
+// there), register-blocked: each thread evaluates R consecutive nodes of one axis-0 line, loading
+// every neighbour row as an R-vector (plus the two axis-0 end values where a mixed (0,k) difference
+// needs them) and sharing index decoding and the axis-1..d coefficient factors across the R nodes.
+template <typename T, int R>
+struct RowV {
+    T v[R + 2];   // v[0] = left neighbour, v[1..R] = nodes, v[R+1] = right neighbour
 };
 
-template <typename T>
-__device__ __forceinline__ LineGeom line_geom(const DevPlan& P, const UnitDev& U, int axis,
-                                              int64_t line, int lm)
+template <typename T, int R>
+__device__ __forceinline__ void load_vec(const T* p, T* dst)
+{
+    typedef T vt __attribute__((ext_vector_type(R)));
+    const vt x = *(const vt*)p;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[r] = x[r];
+}
+
+template <typename T, int D, int OP, int R>
+__global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilArgs A)
+{
+    static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd);
+    const int64_t g = (lb * NODE_BLOCK + threadIdx.x) * R;
+    if (g >= P.total) return;
+    const int u = find_unit(P.units, P.blk_unit_r[R == 4 ? 2 : 1][lb], g);
+    const UnitDev U = P.units[u];
+    const int64_t loc = g - U.off;
+    if (loc >= ((int64_t)1 << U.lsum)) return;   // alignment padding
+    const ProbDev& PR = P.probs[U.prob];
+    const T* tab = (const T*)P.tab;
+    const T* cst = tab + PR.cst;
+
+    int j[D], M[D];
+    int64_t E[D];
+    {
+        int sh = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            M[i] = 1 << U.lv[i];
+            E[i] = (int64_t)1 << sh;
+            j[i] = (int)((loc >> sh) & (M[i] - 1)) + 1;   // j[0] = first of the R nodes
+            sh += U.lv[i];
+        }
+    }
+    const T* X0 = (const T*)A.X0;
+    const T* X1 = (const T*)A.X1;
+    const T av = (T)A.a;
+    const bool has_left = j[0] > 1, has_right = j[0] + R - 1 < M[0];
+    // a row of R nodes at offset o (plus the axis-0 end values when `ends`), zero on faces
+    auto load_row = [&](int64_t o, bool ends, T* v) {
+        load_vec<T, R>(X0 + g + o, v + 1);
+        if constexpr (OP == OP_STAGE2) {
+            T w[R];
+            load_vec<T, R>(X1 + g + o, w);
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
+        }
+        v[0] = T(0);
+        v[R + 1] = T(0);
+        if (ends) {
+            if (has_left) {
+                v[0] = X0[g + o - 1];
+                if constexpr (OP == OP_STAGE2) v[0] += av * X1[g + o - 1];
+            }
+            if (has_right) {
+                v[R + 1] = X0[g + o + R];
+                if constexpr (OP == OP_STAGE2) v[R + 1] += av * X1[g + o + R];
+            }
+        }
+    };
+
+    T c[R + 2];
+    load_row(0, true, c);
+    T acc[R];
+    // axis 0: second differences with the Neumann ghost at j_0 = M_0; coefficients per node
+    const T* t0 = tab + U.tab[0];
+    T tmix0[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int jr = j[0] + r;
+        const T xm = c[r];
+        const T xp = (jr == M[0]) ? xm : c[r + 2];
+        acc[r] = t0[jr - 1] * (xp - T(2) * c[r + 1] + xm);
+        tmix0[r] = t0[M[0] + jr - 1];
+    }
+    // axes 1..D-1: rows at -E_k and +E_k (reflected at j_k = M_k), shared coefficients
+    T tmix[D], tphi[D];
+    const T* tV = tab + U.tab[D - 1];
+    const int MV = M[D - 1];
+    const T vsq = tV[j[D - 1] - 1];
+#pragma unroll
+    for (int k = 1; k < D; ++k) {
+        T rm[R + 2], rp[R + 2];
+        const bool up_ok = j[k] != M[k];
+        if (j[k] > 1) {
+            load_row(-E[k], up_ok, rm);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R + 2; ++r) rm[r] = T(0);
+        }
+        if (up_ok) {
+            load_row(E[k], true, rp);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R + 2; ++r) rp[r] = rm[r];
+        }
+        T td;
+        if (k < D - 1) {
+            const T* tk = tab + U.tab[k];
+            td = tk[j[k] - 1];
+            tmix[k] = tk[M[k] + j[k] - 1];
+            tphi[k] = tk[2 * M[k] + j[k] - 1];
+        } else {
+            td = tV[MV];
+            tmix[k] = tV[MV + 1];
+            tphi[k] = T(0);
+        }
+        // advection on axes 1..D-2 (paper axes 2..N-1), zero on the upper face
+        T adv = T(0);
+        if (k < D - 1 && up_ok) {
+#pragma unroll
+            for (int jj = 1; jj <= k; ++jj) adv += cst[CST_RHO + k * MAXD + jj] * tphi[jj];
+            adv *= tmix[k];
+        }
+        const T c0k = (k < D - 1) ? cst[CST_RHO + 0 * MAXD + k] : cst[CST_SPHI + 0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            acc[r] += td * (rp[r + 1] - T(2) * c[r + 1] + rm[r + 1]);
+            if (k < D - 1 && up_ok) acc[r] += adv * (rp[r + 1] - rm[r + 1]);
+            // mixed (0, k): zero when either node index is on its upper face
+            if (up_ok && (j[0] + r) != M[0]) {
+                const T xx = rp[r + 2] + rm[r] - rp[r] - rm[r + 2];
+                acc[r] += c0k * tmix0[r] * tmix[k] * xx;
+            }
+        }
+    }
+    // mixed (i, k), 1 <= i < k: four diagonal rows of R nodes
+#pragma unroll
+    for (int i = 1; i < D - 1; ++i) {
+#pragma unroll
+        for (int k = i + 1; k < D; ++k) {
+            if (j[i] != M[i] && j[k] != M[k]) {
+                T pp[R + 2], mm[R + 2], pm[R + 2], mp[R + 2];
+                load_row(E[i] + E[k], false, pp);
+                if (j[i] > 1 && j[k] > 1) load_row(-E[i] - E[k], false, mm);
+                else for (int r = 0; r < R + 2; ++r) mm[r] = T(0);
+                if (j[k] > 1) load_row(E[i] - E[k], false, pm);
+                else for (int r = 0; r < R + 2; ++r) pm[r] = T(0);
+                if (j[i] > 1) load_row(-E[i] + E[k], false, mp);
+                else for (int r = 0; r < R + 2; ++r) mp[r] = T(0);
+                const T cik = ((k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i]) * tmix[i] * tmix[k];
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += cik * (pp[r + 1] + mm[r + 1] - pm[r + 1] - mp[r + 1]);
+            }
+        }
+    }
+    const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
+    T* W = (T*)A.W;
+    const T* cG = (const T*)A.cG;
+    T o[R], e[R];
+    if constexpr (OP == OP_STAGE1 || OP == OP_STAGE2) load_vec<T, R>(cG + g, e);
+    if constexpr (OP == OP_REFINE) {
+        load_vec<T, R>(W + g, e);     // K^(0)
+    }
+    T q1[R];
+    if constexpr (OP == OP_STAGE2) load_vec<T, R>(X1 + g, q1);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const T F = vsq * acc[r];
+        if constexpr (OP == OP_STAGE1) o[r] = sc * (F + e[r]);
+        else if constexpr (OP == OP_STAGE2) o[r] = sc * (F + e[r]) + (T)A.q * q1[r];
+        else o[r] = T(2) * e[r] - c[r + 1] + sc * F;
+    }
+    typedef T vt __attribute__((ext_vector_type(R)));
+    vt ov;
+#pragma unroll
+    for (int r = 0; r < R; ++r) ov[r] = o[r];
+    *(vt*)(W + g) = ov;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Directional solves (I - nu dt A_i) x = G (Lemma lema:ls): rows r = 0..M-1 with delta_r =
+// d_i / h_i^2, diagonal 1 + 2 nu dt delta_r, super-diagonal -nu dt delta_r (none in the last row),
+// sub-diagonal -nu dt delta_r (none in the first row, doubled in the last row: Neumann ghost).
+// The matrix of a line depends only on (problem, axis, M_axis, j_V) and dt, so strided axes use
+// Thomas factors (inv_r = 1/pivot_r, a_r inv_r, c'_r) tabulated once per plan in FP64.
+
+template <typename T, int EPI>
+__device__ __forceinline__ void sweep_store(const SweepArgs& A, int64_t idx, T x)
+{
+    if constexpr (EPI == EPI_STORE) {
+        ((T*)A.out)[idx] = x;
+    } else {
+        T* W = (T*)A.out;
+        W[idx] = W[idx] + (T)A.b1 * ((const T*)A.K1)[idx] + (T)A.b2 * x;
+    }
+}
+
+struct Strided {
+    int64_t base;     // element index of row 0
+    int64_t stride;   // E_axis
+    int64_t fac;      // factor block of this line: inv[M], ainv[M], cp[M]
+};
+
+__device__ __forceinline__ Strided strided_geom(const DevPlan& P, const UnitDev& U, int axis,
+                                                int64_t line, int lm, int run)
 {
     const int D = P.d;
     int S = 0, SV = 0;
@@ -190,139 +410,281 @@ __device__ __forceinline__ LineGeom line_geom(const DevPlan& P, const UnitDev& U
     const int64_t E = (int64_t)1 << S;
     const int64_t lo = line & (E - 1), hi = line >> S;
     const int64_t loc0 = lo + (hi << (S + lm));
-    const T* tab = (const T*)P.tab;
-    const T* tV = tab + U.tab[D - 1];
-    const int MV = 1 << U.lv[D - 1];
-    LineGeom L;
+    Strided L;
     L.base = U.off + loc0;
     L.stride = E;
+    L.fac = (int64_t)U.fac[axis] + (int64_t)run * P.fac_run_stride;
     if (axis < D - 1) {
-        const int jV = (int)((loc0 >> SV) & (MV - 1)) + 1;
-        L.dtab = tab + U.tab[axis];
-        L.cmul = (double)tV[jV - 1];
-    } else {
-        L.dtab = tV;
-        L.cmul = (double)tV[MV];
+        const int MV = 1 << U.lv[D - 1];
+        const int64_t jv = (loc0 >> SV) & (MV - 1);
+        L.fac += jv * 3 * ((int64_t)1 << lm);
     }
     return L;
 }
 
-template <typename T, int EPI>
-__device__ __forceinline__ void sweep_store(const SweepArgs& A, int64_t idx, T x)
-{
-    if constexpr (EPI == EPI_STORE) {
-        ((T*)A.out)[idx] = x;
-    } else {
-        T* Y = (T*)A.out;
-        Y[idx] = Y[idx] + (T)A.b1 * ((const T*)A.K1)[idx] + (T)A.b2 * x;
-    }
-}
-
-// Short lines: Thomas with the whole line's factors in registers.
+// Strided axis, line kept in VGPRs: one thread per line, lanes on consecutive lines (coalesced).
 template <typename T, int LM, int EPI>
-__device__ __forceinline__ void sweep_reg(const SweepArgs& A, const LineGeom& L, T nudt)
+__device__ __forceinline__ void sweep_strided_reg(const DevPlan& P, const SweepArgs& A, const Strided& L)
 {
     constexpr int M = 1 << LM;
     const T* in = (const T*)A.in;
-    const T* dt = (const T*)L.dtab;
-    const T cm = (T)L.cmul;
-    T cp[M], dp[M];
+    const T* f = (const T*)P.fac + L.fac;
+    T dp[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-        const T nd = nudt * (dt[r] * cm);
-        const T di = T(1) + T(2) * nd;
-        const T lo = (r == 0) ? T(0) : ((r == M - 1) ? -T(2) * nd : -nd);
-        const T up = (r == M - 1) ? T(0) : -nd;
         const T G = in[L.base + r * L.stride];
-        if (r == 0) {
-            const T inv = T(1) / di;
-            cp[0] = up * inv;
-            dp[0] = G * inv;
-        } else {
-            const T inv = T(1) / (di - lo * cp[r - 1]);
-            cp[r] = up * inv;
-            dp[r] = (G - lo * dp[r - 1]) * inv;
-        }
+        dp[r] = (r == 0) ? G * f[0] : G * f[r] - f[M + r] * dp[r - 1];
     }
     T x = dp[M - 1];
     sweep_store<T, EPI>(A, L.base + (int64_t)(M - 1) * L.stride, x);
 #pragma unroll
     for (int r = M - 2; r >= 0; --r) {
-        x = dp[r] - cp[r] * x;
+        x = dp[r] - f[2 * M + r] * x;
         sweep_store<T, EPI>(A, L.base + r * L.stride, x);
     }
 }
 
-// Long lines: Thomas with c' in the scratch vector and d' in the output (or the consumed input).
+// Strided axis, long line: the forward sweep streams CHUNK rows at a time (loads batched) and leaves
+// d' in memory (the output, or the consumed input when updating); the backward sweep streams it back.
 template <typename T, int EPI>
-__device__ __forceinline__ void sweep_gmem(const SweepArgs& A, const LineGeom& L, T nudt, int lm)
+__device__ __forceinline__ void sweep_strided_mem(const DevPlan& P, const SweepArgs& A, const Strided& L, int lm)
 {
     const int M = 1 << lm;
     const T* in = (const T*)A.in;
     T* dst = (EPI == EPI_STORE) ? (T*)A.out : (T*)A.in;
-    T* cb = (T*)A.cbuf;
-    const T* dt = (const T*)L.dtab;
-    const T cm = (T)L.cmul;
-    T cprev = T(0), dprev = T(0);
-    for (int r = 0; r < M; ++r) {
-        const int64_t idx = L.base + r * L.stride;
-        const T nd = nudt * (dt[r] * cm);
-        const T di = T(1) + T(2) * nd;
-        const T lo = (r == 0) ? T(0) : ((r == M - 1) ? -T(2) * nd : -nd);
-        const T up = (r == M - 1) ? T(0) : -nd;
-        const T inv = T(1) / (di - lo * cprev);
-        const T c = up * inv;
-        const T dd = (in[idx] - lo * dprev) * inv;
-        cb[idx] = c;
-        dst[idx] = dd;
-        cprev = c;
-        dprev = dd;
+    const T* f = (const T*)P.fac + L.fac;
+    T dprev = T(0);
+    for (int c0 = 0; c0 < M; c0 += CHUNK) {
+        T v[CHUNK];
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k) v[k] = in[L.base + (int64_t)(c0 + k) * L.stride];
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k) {
+            const int r = c0 + k;
+            dprev = v[k] * f[r] - f[M + r] * dprev;   // a_0 = 0 makes row 0 start from d' = g inv
+            v[k] = dprev;
+        }
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k) dst[L.base + (int64_t)(c0 + k) * L.stride] = v[k];
     }
-    T x = dprev;
-    sweep_store<T, EPI>(A, L.base + (int64_t)(M - 1) * L.stride, x);
-    for (int r = M - 2; r >= 0; --r) {
-        const int64_t idx = L.base + r * L.stride;
-        x = dst[idx] - cb[idx] * x;
-        sweep_store<T, EPI>(A, idx, x);
+    T x = T(0);                                       // c'_{M-1} = 0: x_{M-1} = d'_{M-1}
+    for (int c0 = M - CHUNK; c0 >= 0; c0 -= CHUNK) {
+        T v[CHUNK];
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k) v[k] = dst[L.base + (int64_t)(c0 + k) * L.stride];
+#pragma unroll
+        for (int k = CHUNK - 1; k >= 0; --k) {
+            x = v[k] - f[2 * M + c0 + k] * x;
+            v[k] = x;
+        }
+#pragma unroll
+        for (int k = 0; k < CHUNK; ++k) sweep_store<T, EPI>(A, L.base + (int64_t)(c0 + k) * L.stride, v[k]);
     }
 }
 
-template <typename T, int EPI>
-__global__ __launch_bounds__(LINE_BLOCK) void k_sweep(DevPlan P, SweepArgs A, int axis)
+template <typename T, int EPI, bool LONG>
+__global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
-    const SweepBlk B = P.ax_blk[axis][blockIdx.x];
+    const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
     const int64_t gl = B.line_start + threadIdx.x;
     if (gl >= B.line_end) return;
     const int64_t* lo = P.ax_line_off[axis];
     int k = B.k_start;
     while (gl >= lo[k + 1]) ++k;
     const UnitDev U = P.units[P.ax_units[axis][k]];
-    const int64_t line = gl - lo[k];
-    const LineGeom L = line_geom<T>(P, U, axis, line, B.lm);
-    const T nudt = ((const T*)P.tab)[P.probs[U.prob].cst + A.nudt_sel];
-    constexpr int RL = sizeof(T) == 8 ? REG_LM_F64 : REG_LM_F32;
-    switch (B.lm) {
-    case 0: sweep_reg<T, 0, EPI>(A, L, nudt); break;
-    case 1: sweep_reg<T, 1, EPI>(A, L, nudt); break;
-    case 2: sweep_reg<T, 2, EPI>(A, L, nudt); break;
-    case 3: sweep_reg<T, 3, EPI>(A, L, nudt); break;
-    case 4: sweep_reg<T, 4, EPI>(A, L, nudt); break;
-    case 5: sweep_reg<T, 5, EPI>(A, L, nudt); break;
-    case 6:
-        if constexpr (RL >= 6) {
-            sweep_reg<T, 6, EPI>(A, L, nudt);
-            break;
+    const Strided L = strided_geom(P, U, axis, gl - lo[k], B.lm, A.run);
+    if constexpr (!LONG) {
+        switch (B.lm) {
+        case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
+        case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
+        case 2: sweep_strided_reg<T, 2, EPI>(P, A, L); break;
+        case 3: sweep_strided_reg<T, 3, EPI>(P, A, L); break;
+        case 4: sweep_strided_reg<T, 4, EPI>(P, A, L); break;
+        default: break;   // long classes go to the LONG launch
         }
-        [[fallthrough]];
-    default: sweep_gmem<T, EPI>(A, L, nudt, B.lm); break;
+    } else {
+        static_assert(REG_LM == 5, "long-line dispatch assumes register lines up to 2^5");
+        if (B.lm == 5) sweep_strided_reg<T, 5, EPI>(P, A, L);
+        else sweep_strided_mem<T, EPI>(P, A, L, B.lm);
+    }
+}
+
+// Axis 0 (contiguous lines).  Coefficients are formed on the fly: delta_r = tdiff_0[r] * V^2.
+struct Contig {
+    int64_t base;
+    const void* tdiff;
+    double vsq;
+};
+
+template <typename T>
+__device__ __forceinline__ Contig contig_geom(const DevPlan& P, const UnitDev& U, int64_t line, int lm)
+{
+    const int D = P.d;
+    int SV = 0;
+    for (int k = 0; k < D - 1; ++k) SV += U.lv[k];
+    const int64_t loc0 = line << lm;
+    const int MV = 1 << U.lv[D - 1];
+    const int jv = (int)((loc0 >> SV) & (MV - 1));
+    const T* tab = (const T*)P.tab;
+    Contig C;
+    C.base = U.off + loc0;
+    C.tdiff = tab + U.tab[0];
+    C.vsq = (double)tab[U.tab[D - 1] + jv];
+    return C;
+}
+
+// Short contiguous line: one thread, Thomas with the line in VGPRs.
+template <typename T, int LM>
+__device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Contig& L, T nudt)
+{
+    constexpr int M = 1 << LM;
+    const T* in = (const T*)A.in + L.base;
+    T* out = (T*)A.out + L.base;
+    const T* td = (const T*)L.tdiff;
+    const T cm = (T)L.vsq;
+    T g[M], cp[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) g[r] = in[r];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const T nd = nudt * (td[r] * cm);
+        const T b = T(1) + T(2) * nd;
+        const T a = (r == 0) ? T(0) : ((r == M - 1) ? -T(2) * nd : -nd);
+        const T c = (r == M - 1) ? T(0) : -nd;
+        const T inv = T(1) / (r == 0 ? b : b - a * cp[r - 1]);
+        cp[r] = c * inv;
+        g[r] = (r == 0) ? g[0] * inv : (g[r] - a * g[r - 1]) * inv;
+    }
+#pragma unroll
+    for (int r = M - 2; r >= 0; --r) g[r] = g[r] - cp[r] * g[r + 1];
+#pragma unroll
+    for (int r = 0; r < M; ++r) out[r] = g[r];
+}
+
+// Long contiguous line: SP = M/SEG lanes, each owning SEG consecutive rows.  Each lane eliminates
+// its first SEG-1 rows in terms of z_{p-1} (last row of the previous segment) and z_p (its own last
+// row): x_k = y_k + v_k z_{p-1} + w_k z_p.  Substituting into the segment-closing rows leaves a
+// tridiagonal system in z_0..z_{SP-1}, solved by parallel cyclic reduction across the SP lanes with
+// wavefront shuffles; the lanes then reconstruct their rows.  Diagonally dominant: no pivoting.
+template <typename T, int SP>
+__device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Contig& L, T nudt, int p)
+{
+    constexpr int S = SEG;
+    const int r0 = p * S;
+    const T* in = (const T*)A.in + L.base + r0;
+    T* out = (T*)A.out + L.base + r0;
+    const T* td = (const T*)L.tdiff + r0;
+    const T cm = (T)L.vsq;
+    const bool first = (p == 0), last = (p == SP - 1);
+    T g[S], cp[S - 1], v[S - 1], w[S - 1];
+#pragma unroll
+    for (int k = 0; k < S; ++k) g[k] = in[k];
+    // interior rows k = 0..S-2 (global r0 + k); row S-1 closes the segment
+    T a_first = T(0);
+#pragma unroll
+    for (int k = 0; k < S - 1; ++k) {
+        const T nd = nudt * (td[k] * cm);
+        const T b = T(1) + T(2) * nd;
+        const T a = (first && k == 0) ? T(0) : -nd;   // interior rows are never the line's last row
+        const T c = -nd;
+        if (k == 0) {
+            a_first = a;
+            const T inv = T(1) / b;
+            cp[0] = (S - 1 == 1) ? T(0) : c * inv;
+            g[0] = g[0] * inv;
+            v[0] = -a * inv;
+            w[0] = (S - 1 == 1) ? -c * inv : T(0);
+        } else {
+            const T inv = T(1) / (b - a * cp[k - 1]);
+            const bool lastint = (k == S - 2);
+            cp[k] = lastint ? T(0) : c * inv;
+            g[k] = (g[k] - a * g[k - 1]) * inv;
+            v[k] = -a * v[k - 1] * inv;
+            w[k] = lastint ? -c * inv : T(0);
+        }
+    }
+#pragma unroll
+    for (int k = S - 3; k >= 0; --k) {
+        g[k] = g[k] - cp[k] * g[k + 1];
+        v[k] = v[k] - cp[k] * v[k + 1];
+        w[k] = w[k] - cp[k] * w[k + 1];
+    }
+    (void)a_first;
+    // segment-closing row r0 + S - 1
+    const T ndl = nudt * (td[S - 1] * cm);
+    const T bl = T(1) + T(2) * ndl;
+    const T al = last ? -T(2) * ndl : -ndl;
+    const T cl = last ? T(0) : -ndl;
+    // first interior row of the next segment (y, v, w)
+    T yF = __shfl_down(g[0], 1, SP), vF = __shfl_down(v[0], 1, SP), wF = __shfl_down(w[0], 1, SP);
+    if (last) yF = vF = wF = T(0);
+    T Ar = al * v[S - 2];
+    T Br = bl + al * w[S - 2] + cl * vF;
+    T Cr = cl * wF;
+    T Rr = g[S - 1] - al * g[S - 2] - cl * yF;
+    // parallel cyclic reduction over the SP lanes of this line
+#pragma unroll
+    for (int s = 1; s < SP; s <<= 1) {
+        T Am = __shfl_up(Ar, s, SP), Bm = __shfl_up(Br, s, SP), Cm = __shfl_up(Cr, s, SP), Rm = __shfl_up(Rr, s, SP);
+        T Ap = __shfl_down(Ar, s, SP), Bp = __shfl_down(Br, s, SP), Cp = __shfl_down(Cr, s, SP), Rp = __shfl_down(Rr, s, SP);
+        if (p < s) { Am = T(0); Bm = T(1); Cm = T(0); Rm = T(0); }
+        if (p + s >= SP) { Ap = T(0); Bp = T(1); Cp = T(0); Rp = T(0); }
+        const T k1 = Ar / Bm, k2 = Cr / Bp;
+        const T nA = -k1 * Am, nC = -k2 * Cp;
+        const T nB = Br - k1 * Cm - k2 * Ap;
+        const T nR = Rr - k1 * Rm - k2 * Rp;
+        Ar = nA; Br = nB; Cr = nC; Rr = nR;
+    }
+    const T z = Rr / Br;
+    T zprev = __shfl_up(z, 1, SP);
+    if (first) zprev = T(0);
+#pragma unroll
+    for (int k = 0; k < S - 1; ++k) out[k] = g[k] + v[k] * zprev + w[k] * z;
+    out[S - 1] = z;
+}
+
+template <typename T, bool LONG>
+__global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArgs A, int64_t blk0)
+{
+    const SweepBlk B = P.ax_blk[0][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
+    const int lm = B.lm;
+    const int sp = lm > CONTIG_REG_LM ? (1 << lm) / SEG : 1;   // lanes per line
+    const int64_t gl = B.line_start + threadIdx.x / sp;
+    if (gl >= B.line_end) return;                              // whole lane groups drop out
+    const int p = threadIdx.x & (sp - 1);
+    const int64_t* lo = P.ax_line_off[0];
+    int k = B.k_start;
+    while (gl >= lo[k + 1]) ++k;
+    const UnitDev U = P.units[P.ax_units[0][k]];
+    const Contig L = contig_geom<T>(P, U, gl - lo[k], lm);
+    const T nudt = ((const T*)P.tab)[P.probs[U.prob].cst + CST_RUN + 3 * A.run + 1];
+    if constexpr (!LONG) {
+        switch (lm) {
+        case 0: sweep_contig_reg<T, 0>(A, L, nudt); break;
+        case 1: sweep_contig_reg<T, 1>(A, L, nudt); break;
+        case 2: sweep_contig_reg<T, 2>(A, L, nudt); break;
+        case 3: sweep_contig_reg<T, 3>(A, L, nudt); break;
+        case 4: sweep_contig_reg<T, 4>(A, L, nudt); break;
+        default: break;
+        }
+    } else {
+        switch (lm) {
+        case 5: sweep_contig_part<T, 2>(A, L, nudt, p); break;
+        case 6: sweep_contig_part<T, 4>(A, L, nudt, p); break;
+        case 7: sweep_contig_part<T, 8>(A, L, nudt, p); break;
+        case 8: sweep_contig_part<T, 16>(A, L, nudt, p); break;
+        case 9: sweep_contig_part<T, 32>(A, L, nudt, p); break;
+        case 10: sweep_contig_part<T, 64>(A, L, nudt, p); break;
+        default: break;   // longer lines are rejected at plan creation
+        }
     }
 }
 
 // ------------------------------------------------------------------------------------------------
-// u_l(x_eval): tensor-product linear interpolation, cell min(floor(x/h), M-1); corners on a lower
-// face take the payoff.  One thread per unit, FP64.
+// u_l(x_eval): tensor-product linear interpolation of Y = W + g, cell min(floor(x/h), M-1); corners
+// on a lower face carry W = 0.  One thread per unit, FP64.
 template <typename T>
-__global__ void k_unit_values(DevPlan P, const T* Y, double* vals)
+__global__ void k_unit_values(DevPlan P, const T* W, double* vals)
 {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= P.n_units) return;
@@ -341,22 +703,22 @@ __global__ void k_unit_values(DevPlan P, const T* Y, double* vals)
     }
     double v = 0.0;
     for (int corner = 0; corner < (1 << D); ++corner) {
-        double w = 1.0;
+        double wgt = 1.0;
         bool onface = false;
         int64_t off = 0;
         int sh = 0;
         double x[MAXD];
         for (int i = 0; i < D; ++i) {
             const int upb = (corner >> i) & 1;
-            w *= upb ? t[i] : 1.0 - t[i];
+            wgt *= upb ? t[i] : 1.0 - t[i];
             const int jc = c[i] + upb;
             x[i] = (double)jc * h[i];
             if (jc == 0) onface = true;
             else off += (int64_t)(jc - 1) << sh;
             sh += U.lv[i];
         }
-        const double val = onface ? payoff_at(PR, D - 1, x) : (double)Y[U.off + off];
-        v += w * val;
+        const double val = (onface ? 0.0 : (double)W[U.off + off]) + payoff_at(PR, D - 1, x);
+        v += wgt * val;
     }
     vals[u] = v;
 }
@@ -382,35 +744,64 @@ __global__ void k_combine(DevPlan P, const double* coef, const double* vals, con
 // ------------------------------------------------------------------------------------------------
 // Launchers
 
-template <typename T>
-static hipError_t init_t(const DevPlan& P, void* Y, hipStream_t s)
+template <typename T, int MODE>
+static hipError_t node_t(const DevPlan& P, const void* W, void* Y, hipStream_t s)
 {
     dim3 g((unsigned)P.n_node_blocks), b(NODE_BLOCK);
     switch (P.d) {
-    case 2: hipLaunchKernelGGL((k_init<T, 2>), g, b, 0, s, P, (T*)Y); break;
-    case 3: hipLaunchKernelGGL((k_init<T, 3>), g, b, 0, s, P, (T*)Y); break;
-    case 4: hipLaunchKernelGGL((k_init<T, 4>), g, b, 0, s, P, (T*)Y); break;
-    case 5: hipLaunchKernelGGL((k_init<T, 5>), g, b, 0, s, P, (T*)Y); break;
-    case 6: hipLaunchKernelGGL((k_init<T, 6>), g, b, 0, s, P, (T*)Y); break;
+    case 2: hipLaunchKernelGGL((k_node<T, 2, MODE>), g, b, 0, s, P, (const T*)W, (T*)Y); break;
+    case 3: hipLaunchKernelGGL((k_node<T, 3, MODE>), g, b, 0, s, P, (const T*)W, (T*)Y); break;
+    case 4: hipLaunchKernelGGL((k_node<T, 4, MODE>), g, b, 0, s, P, (const T*)W, (T*)Y); break;
+    case 5: hipLaunchKernelGGL((k_node<T, 5, MODE>), g, b, 0, s, P, (const T*)W, (T*)Y); break;
+    case 6: hipLaunchKernelGGL((k_node<T, 6, MODE>), g, b, 0, s, P, (const T*)W, (T*)Y); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_init(const DevPlan& P, int prec, void* Y, hipStream_t s)
+hipError_t launch_payoff(const DevPlan& P, int prec, void* Y, hipStream_t s)
 {
     if (P.total == 0) return hipSuccess;
-    return prec == 0 ? init_t<double>(P, Y, s) : init_t<float>(P, Y, s);
+    return prec == 0 ? node_t<double, 0>(P, nullptr, Y, s) : node_t<float, 0>(P, nullptr, Y, s);
+}
+
+hipError_t launch_fill_zero(const DevPlan& P, int prec, void* Y, hipStream_t s)
+{
+    if (P.total == 0) return hipSuccess;
+    return prec == 0 ? node_t<double, 1>(P, nullptr, Y, s) : node_t<float, 1>(P, nullptr, Y, s);
+}
+
+hipError_t launch_state_read(const DevPlan& P, int prec, const void* W, void* Y, hipStream_t s)
+{
+    if (P.total == 0) return hipSuccess;
+    return prec == 0 ? node_t<double, 2>(P, W, Y, s) : node_t<float, 2>(P, W, Y, s);
+}
+
+template <typename T, int D, int R>
+static hipError_t stencil_vec(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
+{
+    dim3 g((unsigned)P.n_blocks_r[R == 4 ? 2 : 1]), b(NODE_BLOCK);
+    switch (op) {
+    case OP_STAGE1: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R>), g, b, 0, s, P, a); break;
+    case OP_STAGE2: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R>), g, b, 0, s, P, a); break;
+    case OP_REFINE: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R>), g, b, 0, s, P, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int D>
 static hipError_t stencil_td(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
+    const bool hot = op == OP_STAGE1 || op == OP_STAGE2 || op == OP_REFINE;
+    if (hot && P.stencil_r == 4) return stencil_vec<T, D, 4>(P, op, a, s);
+    if (hot && P.stencil_r == 2) return stencil_vec<T, D, 2>(P, op, a, s);
     dim3 g((unsigned)P.n_node_blocks), b(NODE_BLOCK);
     switch (op) {
     case OP_F_PAYOFF: hipLaunchKernelGGL((k_stencil<T, D, OP_F_PAYOFF>), g, b, 0, s, P, a); break;
     case OP_F_ZERO: hipLaunchKernelGGL((k_stencil<T, D, OP_F_ZERO>), g, b, 0, s, P, a); break;
-    case OP_STAGE: hipLaunchKernelGGL((k_stencil<T, D, OP_STAGE>), g, b, 0, s, P, a); break;
+    case OP_STAGE1: hipLaunchKernelGGL((k_stencil<T, D, OP_STAGE1>), g, b, 0, s, P, a); break;
+    case OP_STAGE2: hipLaunchKernelGGL((k_stencil<T, D, OP_STAGE2>), g, b, 0, s, P, a); break;
     case OP_REFINE: hipLaunchKernelGGL((k_stencil<T, D, OP_REFINE>), g, b, 0, s, P, a); break;
     default: return hipErrorInvalidValue;
     }
@@ -436,28 +827,40 @@ hipError_t launch_stencil(const DevPlan& P, int prec, int op, const StencilArgs&
     return prec == 0 ? stencil_t<double>(P, op, a, s) : stencil_t<float>(P, op, a, s);
 }
 
-template <typename T>
-static hipError_t sweep_t(const DevPlan& P, int axis, int epi, const SweepArgs& a, hipStream_t s)
+template <typename T, bool LONG>
+static void sweep_part(const DevPlan& P, int axis, int epi, const SweepArgs& a, int64_t b0, int64_t nb,
+                       hipStream_t s)
 {
-    dim3 g((unsigned)P.ax_nblk[axis]), b(LINE_BLOCK);
-    if (epi == EPI_STORE) hipLaunchKernelGGL((k_sweep<T, EPI_STORE>), g, b, 0, s, P, a, axis);
-    else hipLaunchKernelGGL((k_sweep<T, EPI_UPDATE>), g, b, 0, s, P, a, axis);
+    dim3 g((unsigned)nb), b(LINE_BLOCK);
+    if (axis == 0) hipLaunchKernelGGL((k_sweep_contig<T, LONG>), g, b, 0, s, P, a, b0);
+    else if (epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE, LONG>), g, b, 0, s, P, a, axis, b0);
+    else hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE, LONG>), g, b, 0, s, P, a, axis, b0);
+}
+
+hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part, const SweepArgs& a,
+                        hipStream_t s)
+{
+    if (axis == 0 && epi != EPI_STORE) return hipErrorInvalidValue;
+    const int64_t ns = P.ax_nblk_short[axis];
+    const int64_t b0 = part == 0 ? 0 : ns;
+    const int64_t nb = part == 0 ? ns : P.ax_nblk[axis] - ns;
+    if (nb <= 0) return hipSuccess;
+    if (prec == 0) {
+        if (part == 0) sweep_part<double, false>(P, axis, epi, a, b0, nb, s);
+        else sweep_part<double, true>(P, axis, epi, a, b0, nb, s);
+    } else {
+        if (part == 0) sweep_part<float, false>(P, axis, epi, a, b0, nb, s);
+        else sweep_part<float, true>(P, axis, epi, a, b0, nb, s);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, const SweepArgs& a,
-                        hipStream_t s)
-{
-    if (P.ax_nblk[axis] == 0) return hipSuccess;
-    return prec == 0 ? sweep_t<double>(P, axis, epi, a, s) : sweep_t<float>(P, axis, epi, a, s);
-}
-
-hipError_t launch_unit_values(const DevPlan& P, int prec, const void* Y, double* vals, hipStream_t s)
+hipError_t launch_unit_values(const DevPlan& P, int prec, const void* W, double* vals, hipStream_t s)
 {
     if (P.n_units == 0) return hipSuccess;
     dim3 g((P.n_units + 127) / 128), b(128);
-    if (prec == 0) hipLaunchKernelGGL((k_unit_values<double>), g, b, 0, s, P, (const double*)Y, vals);
-    else hipLaunchKernelGGL((k_unit_values<float>), g, b, 0, s, P, (const float*)Y, vals);
+    if (prec == 0) hipLaunchKernelGGL((k_unit_values<double>), g, b, 0, s, P, (const double*)W, vals);
+    else hipLaunchKernelGGL((k_unit_values<float>), g, b, 0, s, P, (const float*)W, vals);
     return hipGetLastError();
 }
 

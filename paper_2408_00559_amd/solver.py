@@ -99,6 +99,11 @@ class Plan:
         return int(self.info.inner_points)
 
     @property
+    def vector_len(self) -> int:
+        """Elements of one grid vector (inner points of all units plus alignment padding)."""
+        return int(self.info.vector_bytes) // (8 if self.dtype == torch.float64 else 4)
+
+    @property
     def stage_updates(self) -> int:
         return int(self.info.stage_updates_per_solve)
 
@@ -135,21 +140,21 @@ class Plan:
         L.check(L.lib().amf_unit_values(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
-    def state(self) -> torch.Tensor:
-        """View of the solution vector Y (inner-node layout, plan precision)."""
-        off = self._ws_off + int(self.info.state_offset)
-        nb = int(self.info.vector_bytes)
-        return self.workspace[off:off + nb].view(self.dtype)
+    def state(self, stream=None) -> torch.Tensor:
+        """The current solution Y (inner-node layout of all units, plan precision), as a copy."""
+        out = torch.empty(self.vector_len, dtype=self.dtype, device=self.device)
+        L.check(L.lib().amf_state_read(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
 
     def apply_operator(self, x: torch.Tensor, increment: bool, scale: float = 1.0, stream=None) -> torch.Tensor:
-        assert x.dtype == self.dtype and x.numel() == self.inner_points and x.is_contiguous()
+        assert x.dtype == self.dtype and x.numel() == self.vector_len and x.is_contiguous()
         out = torch.empty_like(x)
         L.check(L.lib().amf_apply_operator(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
                                            1 if increment else 0, float(scale), _stream(stream)))
         return out
 
     def axis_solve(self, axis: int, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
-        assert x.dtype == self.dtype and x.numel() == self.inner_points and x.is_contiguous()
+        assert x.dtype == self.dtype and x.numel() == self.vector_len and x.is_contiguous()
         if out is None:
             out = torch.empty_like(x)
         L.check(L.lib().amf_axis_solve(self._h, int(axis), C.c_void_p(x.data_ptr()),
@@ -159,6 +164,20 @@ class Plan:
     def price(self, stream=None) -> torch.Tensor:
         self.solve(stream)
         return self.combine(stream=stream)
+
+    def schedule(self) -> dict:
+        sc = L.AmfSchedule()
+        L.check(L.lib().amf_schedule_get(self._h, C.byref(sc)))
+        return dict(stencil_nodes=sc.stencil_nodes, xcd_remap=sc.xcd_remap,
+                    max_stencil_nodes=sc.max_stencil_nodes)
+
+    def set_schedule(self, stencil_nodes: int | None = None, xcd_remap: int | None = None):
+        cur = self.schedule()
+        sc = L.AmfSchedule()
+        sc.struct_size = C.sizeof(L.AmfSchedule)
+        sc.stencil_nodes = cur["stencil_nodes"] if stencil_nodes is None else int(stencil_nodes)
+        sc.xcd_remap = cur["xcd_remap"] if xcd_remap is None else int(xcd_remap)
+        L.check(L.lib().amf_schedule_set(self._h, C.byref(sc)))
 
     def profile_begin(self):
         L.check(L.lib().amf_profile_begin(self._h))

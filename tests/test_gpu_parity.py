@@ -40,7 +40,7 @@ CASES = _cases()
 
 def _random_inner(plan, seed):
     rng = np.random.default_rng(seed)
-    return rng.uniform(-1.0, 1.0, plan.inner_points)
+    return rng.uniform(-1.0, 1.0, plan.vector_len)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -85,7 +85,9 @@ def test_axis_solves(name):
         out = plan.axis_solve(ax, gt).cpu().numpy()
         inplace = gt.clone()
         plan.axis_solve(ax, inplace, out=inplace)
-        assert np.array_equal(out, inplace.cpu().numpy())
+        inp = inplace.cpu().numpy()
+        for u, sl in unit_slices(plan):        # padding between units is never written
+            assert np.array_equal(out[sl], inp[sl])
         for u, sl in unit_slices(plan):
             p = probs[u["problem"]]
             lv = u["levels"]
@@ -189,3 +191,47 @@ def test_determinism_and_restart():
     plan.time_step(3)
     c = plan.combine().cpu().numpy()
     assert np.array_equal(a, c)
+
+
+@pytest.mark.parametrize("name", ["fg2d", "d3_ct", "d4_ct", "d6_ct", "long_rate_axis"])
+def test_schedules_agree(name):
+    """Every launch schedule (operator nodes per thread, XCD remapping) gives the oracle's step."""
+    probs, grid = CASES[name]
+    steps = 5
+    plan = Plan(probs, grid, steps=steps, device=DEV)
+    mx = plan.schedule()["max_stencil_nodes"]
+    items = unit_slices(plan)
+
+    def ref(item):
+        u, sl = item
+        p = probs[u["problem"]]
+        lv = u["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / steps, 2)
+        return oracle.inner_view(Yf, lv)
+
+    refs = parallel(ref, items)
+    for r in (1, 2, 4):
+        if r > mx:
+            continue
+        for x in (0, 1):
+            plan.set_schedule(stencil_nodes=r, xcd_remap=x)
+            plan.init()
+            plan.time_step(2)
+            Y = plan.state().cpu().numpy()
+            for (u, sl), rr in zip(items, refs):
+                assert rel_maxerr(Y[sl], rr) < 1e-12, (r, x, u)
+
+
+def test_autotune_picks_admissible_schedule(tmp_path, monkeypatch):
+    from paper_2408_00559_amd import autotune
+    monkeypatch.setenv("AMF_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    probs, grid = CASES["d4_ct"]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    res = autotune.tune(plan, steps=1, reps=1)
+    assert res["schedule"] in autotune.candidates(plan)
+    assert plan.schedule()["stencil_nodes"] == res["schedule"]["stencil_nodes"]
+    again = autotune.tune(plan, steps=1, reps=1)
+    assert again["cached"] and again["schedule"] == res["schedule"]
+    ref = oracle.price(probs[0], grid, 4)
+    assert abs(plan.price().cpu().numpy()[0] - ref) / abs(ref) < 1e-10

@@ -94,6 +94,7 @@ def test_units_match_combination_formula(orc, d, n, psi):
     olv, ocf = orc.ct_grids(d, n, psi)
     assert info.n_units == 2 * len(ocf)
     total = 0
+    inner = 0
     for u in range(info.n_units):
         prob = C.c_int32()
         lv = (C.c_int32 * 8)()
@@ -104,10 +105,12 @@ def test_units_match_combination_formula(orc, d, n, psi):
         assert prob.value == u // len(ocf)
         assert [lv[i] for i in range(d)] == list(olv[g])
         assert cf.value == ocf[g]
-        assert off.value == total
-        total += 1 << int(sum(olv[g]))
-    assert info.inner_points == total
-    assert info.stage_updates_per_solve == total * 2 * 10
+        assert off.value % 64 == 0 and off.value >= total
+        total = off.value + (1 << int(sum(olv[g])))
+        inner += 1 << int(sum(olv[g]))
+    assert info.inner_points == inner
+    assert info.stage_updates_per_solve == inner * 2 * 10
+    assert info.vector_bytes >= 8 * total
     lib.amf_plan_destroy(h)
 
 
