@@ -166,6 +166,91 @@ def run_form(torch, Plan, w, precision, steps, warmup, tune=True):
     return out
 
 
+def run_serving(torch, Plan, batches=10):
+    """Batched serving: 512 seeded parameter sets (d = 4, modified combination n = 6, psi = 1,
+    100 steps), FP32 stencil and sweeps with FP64 combination, the whole solve replayed as one
+    hipGraph.  Latency per price = submit-to-host-result time of its batch."""
+    import numpy as np
+
+    from paper_2408_00559_amd import autotune
+    from paper_2408_00559_amd import inputs as I
+
+    w = I.workload_batch4()
+    n = len(w["problems"])
+    ref64 = Plan(w["problems"], w["grid"], w["steps"], precision="fp64", device="cuda:0")
+    autotune.tune(ref64, steps=1, reps=1)
+    p64 = ref64.price().cpu().numpy()
+    del ref64
+    torch.cuda.empty_cache()
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp32", device="cuda:0")
+    tuned = autotune.tune(plan, steps=1, reps=1)
+    plan.use_graph(True)
+    prices = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    plan.solve()
+    plan.combine(prices)
+    torch.cuda.synchronize()
+    lat = []
+    host = None
+    for _ in range(batches):
+        t0 = time.perf_counter()
+        plan.solve()
+        plan.combine(prices)
+        host = prices.cpu().numpy()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat)
+    rel = np.abs(host - p64) / np.abs(p64)
+    golden = os.path.join(ROOT, "tests", "golden", "batch4_first16_fp64.json")
+    rel_oracle = None
+    if os.path.exists(golden):
+        g = json.load(open(golden))
+        k = g["count"]
+        rel_oracle = float(np.max(np.abs(host[:k] - np.array(g["prices"])) / np.abs(np.array(g["prices"]))))
+    out = {"workload": w["name"], "instances": n, "component_grids": plan.n_units,
+           "inner_points": plan.inner_points, "dtype": "f32 (FP64 combine)", "graph": True,
+           "batches": batches, "prices_per_s": n / float(np.median(lat)),
+           "stage_updates_per_s": plan.stage_updates / float(np.median(lat)),
+           "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                         "min": float(lat.min()), "max": float(lat.max())},
+           "max_rel_err_vs_fp64": float(rel.max()), "max_rel_err_vs_oracle_first16": rel_oracle,
+           "schedule": plan.schedule(), "autotune_cached": tuned.get("cached")}
+    del plan
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_ct6(torch, Plan):
+    """d = 6 (5 rates + V), modified combination n = 8, psi = 1 (2975 component grids): FP32
+    stencil and sweeps with FP64 combination, fourth order in time by Richardson extrapolation of
+    AMFR-W2 over 200 and 400 steps; error per price against the FP64 run of the same scheme."""
+    from paper_2408_00559_amd import autotune
+    from paper_2408_00559_amd import inputs as I
+
+    w = I.workload_ct6()
+    res = {}
+    for prec in ("fp32", "fp64"):
+        plan = Plan(w["problems"], w["grid"], w["steps"], precision=prec, richardson=True, device="cuda:0")
+        autotune.tune(plan, steps=2, reps=1)
+        plan.use_graph(True)
+        pr = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        plan.solve()
+        plan.combine(pr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve()
+        plan.combine(pr)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        res[prec] = {"price": float(pr.item()), "sec_per_solve": sec,
+                     "stage_updates_per_s": plan.stage_updates / sec, "schedule": plan.schedule()}
+        units, pts, su = plan.n_units, plan.inner_points, plan.stage_updates
+        del plan
+        torch.cuda.empty_cache()
+    res["rel_err_fp32_vs_fp64"] = abs(res["fp32"]["price"] - res["fp64"]["price"]) / abs(res["fp64"]["price"])
+    res.update({"workload": w["name"], "component_grids": units, "inner_points": pts,
+                "stage_updates_per_solve": su, "time_steps": "200 + 400 (Richardson)"})
+    return res
+
+
 def cpu_baseline(w, max_seconds_hint=20.0):
     """The FP64 oracle on a bounded sample of the same workload: the smallest combination layer
     (35 component grids of 65,536 inner points) for a few of the 100 time steps, all host cores."""
@@ -225,6 +310,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-ct6", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/hbm_traffic_ct4.json from two rocprofv3 --pmc runs")
     ap.add_argument("--pmc-precision", default="fp64")
@@ -289,6 +376,10 @@ def main():
                        "rel_err_against": "oracle" if ref else "fp64 GPU",
                        "roofline": f32["roofline"], "kernels": f32["kernels"],
                        "schedule": f32["schedule"], "autotune": f32["autotune"]}
+    if not args.no_serving:
+        res["serving_batch4"] = run_serving(torch, Plan)
+    if not args.no_ct6:
+        res["ct6_fp32_richardson"] = run_ct6(torch, Plan)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

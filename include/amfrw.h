@@ -155,6 +155,11 @@ amf_status amf_time_step(amf_plan* plan, int32_t n, void* stream);
 /* amf_init + n_steps steps (and the 2*n_steps fine run when richardson = 1). */
 amf_status amf_solve(amf_plan* plan, void* stream);
 
+/* on = 1: amf_solve replays one hipGraph holding the whole solve (captured on the first call after
+ * enabling, binding or changing the schedule; kernels only, no memset or copy nodes) instead of
+ * launching ~10 d kernels per step from the host.  Not used while per-kernel profiling is on. */
+amf_status amf_graph_enable(amf_plan* plan, int32_t on);
+
 /* Per-unit value u_l(x_eval) by tensor-product linear interpolation (Section 5), in FP64, one per
  * unit in unit order, written to d_values (device, n_units doubles). */
 amf_status amf_unit_values(amf_plan* plan, double* d_values, void* stream);

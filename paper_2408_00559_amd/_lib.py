@@ -110,6 +110,8 @@ def lib():
         L.amf_time_step.argtypes = [vp, C.c_int32, vp]
         L.amf_solve.restype = st
         L.amf_solve.argtypes = [vp, vp]
+        L.amf_graph_enable.restype = st
+        L.amf_graph_enable.argtypes = [vp, C.c_int32]
         L.amf_unit_values.restype = st
         L.amf_unit_values.argtypes = [vp, vp, vp]
         L.amf_combine.restype = st
@@ -141,5 +143,5 @@ def check(status: int):
 
 EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_plan_create",
             "amf_plan_info_get", "amf_unit_info", "amf_plan_bind", "amf_init", "amf_time_step",
-            "amf_solve", "amf_unit_values", "amf_combine", "amf_state_read", "amf_apply_operator",
+            "amf_solve", "amf_graph_enable", "amf_unit_values", "amf_combine", "amf_state_read", "amf_apply_operator",
             "amf_axis_solve", "amf_schedule_get", "amf_schedule_set", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy"]

@@ -77,11 +77,28 @@ struct amf_plan {
     size_t pool_next = 0;
     std::vector<ProfRec> recs;
 
+    // whole-solve hipGraph (captured on first use, replayed by amf_solve)
+    bool graph_on = false, graph_valid = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;
+
     void* vec(int v) const { return ws + off_vec[v]; }
     double vbytes() const { return (double)total * (double)elem; }
 
+    void drop_graph()
+    {
+        if (graph_exec) (void)hipGraphExecDestroy(graph_exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        graph_exec = nullptr;
+        graph = nullptr;
+        graph_valid = false;
+    }
+
     ~amf_plan()
     {
+        drop_graph();
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
     }
 };
@@ -532,6 +549,7 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
     if (bytes < P->ws_bytes) return fail(AMF_E_INVALID, "workspace too small: need " + std::to_string(P->ws_bytes) + " bytes");
     if (((uintptr_t)d_ws & 255u) != 0) return fail(AMF_E_INVALID, "workspace must be 256-byte aligned");
     hipStream_t s = (hipStream_t)stream;
+    P->drop_graph();
     P->ws = (char*)d_ws;
     P->bound = false;
     P->initialised = false;
@@ -773,23 +791,78 @@ amf_status amf_time_step(amf_plan* P, int32_t n, void* stream)
     return AMF_OK;
 }
 
-amf_status amf_solve(amf_plan* P, void* stream)
+namespace {
+
+// The whole solve (initial data, n_steps steps, and the fine run of a Richardson pair) on stream s.
+amf_status solve_body(amf_plan* P, hipStream_t s)
 {
-    amf_status st = check_bound(P);
-    if (st) return st;
-    hipStream_t s = (hipStream_t)stream;
-    if ((st = amf_init(P, stream))) return st;
+    amf_status st;
+    hipError_t e = run_init(P, s);
+    if (e != hipSuccess) return hip_fail(e, "init");
     for (int i = 0; i < P->steps; ++i)
         if ((st = one_step(P, 0, s))) return st;
     if (P->richardson) {
-        hipError_t e = run_unit_values(P, (double*)(P->ws + P->off_valsc), s);
+        e = run_unit_values(P, (double*)(P->ws + P->off_valsc), s);
         if (e != hipSuccess) return hip_fail(e, "unit values");
         if ((e = timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_fill_zero(P->dev, P->prec, P->vec(V_W), s); })) != hipSuccess)
             return hip_fail(e, "init");
         for (int i = 0; i < 2 * P->steps; ++i)
             if ((st = one_step(P, 1, s))) return st;
-        P->have_coarse = true;
     }
+    return AMF_OK;
+}
+
+amf_status capture_graph(amf_plan* P)
+{
+    hipError_t e;
+    if (!P->cap_stream && (e = hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    if ((e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "hipStreamBeginCapture");
+    amf_status st = solve_body(P, P->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(P->cap_stream, &g);
+    if (st != AMF_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t gx = nullptr;
+    if ((e = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    P->graph = g;
+    P->graph_exec = gx;
+    P->graph_valid = true;
+    return AMF_OK;
+}
+
+}  // namespace
+
+amf_status amf_graph_enable(amf_plan* P, int32_t on)
+{
+    if (!P) return fail(AMF_E_INVALID, "null plan");
+    if (on != 0 && on != 1) return fail(AMF_E_INVALID, "on must be 0 or 1");
+    if (!on) P->drop_graph();
+    P->graph_on = on != 0;
+    return AMF_OK;
+}
+
+amf_status amf_solve(amf_plan* P, void* stream)
+{
+    amf_status st = check_bound(P);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (P->graph_on && !P->prof) {
+        if (!P->graph_valid && (st = capture_graph(P))) return st;
+        hipError_t e = hipGraphLaunch(P->graph_exec, s);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        if ((st = solve_body(P, s))) return st;
+    }
+    P->initialised = true;
+    P->have_coarse = P->richardson != 0;
     return AMF_OK;
 }
 
@@ -880,6 +953,7 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (r != 1 && r != 2 && r != 4) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2 or 4");
     if (r > P->min_m0) return fail(AMF_E_INVALID, "stencil_nodes exceeds the smallest axis-1 line");
     if (sc->xcd_remap != 0 && sc->xcd_remap != 1) return fail(AMF_E_INVALID, "xcd_remap must be 0 or 1");
+    if (r != P->stencil_r || sc->xcd_remap != P->xcd) P->drop_graph();
     P->stencil_r = r;
     P->xcd = sc->xcd_remap;
     P->dev.stencil_r = r;

@@ -129,6 +129,9 @@ class Plan:
     def solve(self, stream=None):
         L.check(L.lib().amf_solve(self._h, _stream(stream)))
 
+    def use_graph(self, on: bool = True):
+        L.check(L.lib().amf_graph_enable(self._h, 1 if on else 0))
+
     def combine(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         if out is None:
             out = torch.empty(len(self.problems), dtype=torch.float64, device=self.device)

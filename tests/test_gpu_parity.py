@@ -235,3 +235,36 @@ def test_autotune_picks_admissible_schedule(tmp_path, monkeypatch):
     assert again["cached"] and again["schedule"] == res["schedule"]
     ref = oracle.price(probs[0], grid, 4)
     assert abs(plan.price().cpu().numpy()[0] - ref) / abs(ref) < 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_graph_replays_match_eager(precision):
+    """a9: the hipGraph-captured solve equals the eagerly launched one bitwise on every replay, with
+    unrelated eager work and host synchronisations between the replays."""
+    probs = I.draw_instances(6, seed=21, d=4)
+    plan = Plan(probs, I.combination(4, 1), 6, precision=precision, device=DEV)
+    eager = plan.price().cpu().numpy()
+    plan.use_graph(True)
+    x = torch.ones(plan.vector_len, dtype=plan.dtype, device=DEV)
+    for rep in range(4):
+        got = plan.price().cpu().numpy()
+        assert np.array_equal(got, eager), rep
+        plan.apply_operator(x, increment=True)          # eager work between replays
+        torch.cuda.synchronize()
+    plan.set_schedule(stencil_nodes=1)                   # schedule change re-captures
+    assert np.allclose(plan.price().cpu().numpy(), eager, rtol=1e-12 if precision == "fp64" else 1e-6)
+    plan.use_graph(False)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_batched_instances(precision, tol):
+    """a9/a10: many seeded parameter sets (uneven beta, sigma, phi, strikes) in one plan."""
+    probs = I.draw_instances(24, seed=4, d=4)
+    grid = I.combination(3, 1)
+    steps = 10
+    plan = Plan(probs, grid, steps, precision=precision, device=DEV)
+    plan.use_graph(True)
+    prices = plan.price().cpu().numpy()
+    refs = parallel(lambda p: oracle.price(p, grid, steps, nthreads=1), probs)
+    for got, ref in zip(prices, refs):
+        assert abs(got - ref) / abs(ref) < tol, (got, ref)
