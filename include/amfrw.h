@@ -236,6 +236,54 @@ amf_status amf_profile_begin(amf_plan* plan);
 /* stats: array of AMF_K_COUNT entries (one per class, in class order). */
 amf_status amf_profile_end(amf_plan* plan, amf_kernel_stat* stats);
 
+/* ------------------------------------------------------------------------------------------------
+ * Pricing surrogate: a fully connected network n_in -> width (x depth, SiLU) -> 2 with BF16 weights
+ * and activations and FP32 accumulation (gfx950 MFMA), trained on prices of the solver above.
+ * Output 0 is the price, output 1 the logarithm of its estimated absolute error; callers route
+ * requests whose estimated relative error exceeds their tolerance to the solver.  All shapes are
+ * fixed at creation; device memory is caller-owned (one workspace, bound like a plan's). */
+typedef struct amf_mlp amf_mlp;
+
+typedef struct {
+    int64_t n_params;                 /* FP32 master parameters (padded layout, see below)         */
+    uint64_t workspace_bytes;
+    int32_t n_in, width, depth, n_out, max_batch, layers;
+    /* Parameter layout: per layer l a row-major weight block of layer_rows x layer_cols floats at
+     * layer_w_offset, then layer_rows biases at layer_b_offset.  Rows and columns beyond the
+     * logical sizes are zero padding and stay zero. */
+    int32_t layer_rows[8], layer_cols[8];
+    int64_t layer_w_offset[8], layer_b_offset[8];
+} amf_mlp_info;
+
+const char* amf_mlp_last_error(void);
+/* n_in in [1, 32]; width a multiple of 32 in [32, 1024]; depth (hidden layers) in [1, 7]; n_out = 2;
+ * weights drawn U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from `seed` (SplitMix64), biases 0. */
+amf_status amf_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_out, int32_t max_batch,
+                          uint64_t seed, amf_mlp** out);
+amf_status amf_mlp_info_get(const amf_mlp* mlp, amf_mlp_info* out);
+/* Bind the workspace and upload the initial parameters (synchronises the stream). */
+amf_status amf_mlp_bind(amf_mlp* mlp, void* d_workspace, uint64_t bytes, void* stream);
+/* Host arrays: feature means and standard deviations (n_in each), price mean and scale (1 each). */
+amf_status amf_mlp_set_normalization(amf_mlp* mlp, const float* in_mean, const float* in_std,
+                                     const float* out_mean, const float* out_std, void* stream);
+/* direction 0: copy the FP32 master parameters to d_params; 1: load them from d_params (device). */
+amf_status amf_mlp_params(amf_mlp* mlp, float* d_params, int32_t direction, void* stream);
+/* Copy the gradient of the last backward pass / training step (same layout as the parameters). */
+amf_status amf_mlp_grads(amf_mlp* mlp, float* d_grads, void* stream);
+/* d_x: [batch, n_in] raw features (FP32, device).  d_out: [batch, 2] = (price, estimated relative
+ * error of the price). */
+amf_status amf_mlp_forward(amf_mlp* mlp, const float* d_x, int32_t batch, float* d_out, void* stream);
+/* After amf_mlp_forward of the same batch: gradient of sum_b dy[b] . y[b] with respect to the
+ * parameters, y the two raw network outputs; d_dy is [batch, 2] FP32. */
+amf_status amf_mlp_backward(amf_mlp* mlp, const float* d_dy, int32_t batch, void* stream);
+/* One Adam step (beta 0.9/0.999, eps 1e-8) on the loss
+ *   mean_b (y0 - t_b)^2 + err_weight (y1 - log(|y0 - t_b| + 1e-6))^2,  t_b the normalised target price;
+ * the residual in the second term is held constant.  d_loss (device, optional) receives the batch
+ * sum before the division by the batch size. */
+amf_status amf_mlp_train_step(amf_mlp* mlp, const float* d_x, const float* d_target, int32_t batch,
+                              float lr, float err_weight, float* d_loss, void* stream);
+void amf_mlp_destroy(amf_mlp* mlp);
+
 /* Release host resources.  Device memory stays owned by the caller.  NULL is allowed. */
 void amf_plan_destroy(amf_plan* plan);
 

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libamfrw.so")
 OBJDIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["amfrw_host.cpp", "amfrw_kernels.hip"]
+SOURCES = ["amfrw_host.cpp", "amfrw_kernels.hip", "amfrw_mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -291,7 +291,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         gcf.push_back(1.0);
     } else {
         if (grid->psi < 0 || grid->psi > 8) return fail(AMF_E_INVALID, "psi must lie in [0, 8]");
-        if (grid->n < d - 1) return fail(AMF_E_INVALID, "n must be >= d-1");
+        if (grid->n < d - 1) return fail(AMF_E_INVALID, "n must be >= d-1 (combination coefficients sum to 1)");
         if (grid->psi + grid->n > 16 || d * grid->psi + grid->n > 30)
             return fail(AMF_E_INVALID, "combination level too large");
         if (grid->psi + grid->n > 10) return fail(AMF_E_UNSUPPORTED, "axis-1 level above 10 is not built");

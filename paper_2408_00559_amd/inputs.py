@@ -12,7 +12,7 @@ lower faces, homogeneous Neumann on the upper faces (eq. bound1).
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field, replace
+from dataclasses import dataclass
 from typing import List, Optional
 
 import numpy as np
@@ -134,13 +134,24 @@ def workload_ct4(seed: int = 2, n: int = 7, psi: int = 3, steps: int = 100) -> d
                 richardson=False)
 
 
+DOMAIN_FACTOR_D6 = 4.0   # d = 6: upper boundaries at 4x the evaluation point (Section 6 practice)
+
+
+def relative_domain(p: Problem, factor: float = DOMAIN_FACTOR_D6) -> Problem:
+    """Upper boundaries at `factor` times the evaluation point on every axis, as the paper places
+    them between 3 and 4 times the point of interest (Section 6)."""
+    p.xmax = [factor * x for x in p.xeval]
+    return p
+
+
 def workload_ct6(seed: int = 3, n: int = 8, psi: int = 1, steps: int = 200) -> dict:
     """d = 6 (5 rates + V), modified combination n = 8, psi = 1; parameters drawn as for the d = 4
-    workload; Richardson-extrapolated AMFR-W2 (steps and 2*steps) for fourth order in time."""
+    workload, domain 4x the evaluation point; Richardson-extrapolated AMFR-W2 (steps and 2*steps)
+    for fourth order in time."""
     rng = np.random.default_rng(seed)
     F0 = float(rng.uniform(0.02, 0.05))
     V0 = float(rng.uniform(0.15, 0.35))
-    p = _sabr_instance(6, 0.5, 0.3, -0.3, F0, V0, F0, 1.0, 0.1, SWAPTION)
+    p = relative_domain(_sabr_instance(6, 0.5, 0.3, -0.3, F0, V0, F0, 1.0, 0.1, SWAPTION))
     return dict(name=f"ct6_n{n}_psi{psi}", problems=[p], grid=combination(n, psi), steps=steps,
                 richardson=True)
 
@@ -167,6 +178,19 @@ def draw_instances(count: int, seed: int, d: int = 4, T_range=None, lam_range=No
 def workload_batch4(count: int = 512, seed: int = 4, n: int = 6, psi: int = 1, steps: int = 100) -> dict:
     """Batched serving: `count` seeded parameter sets, d = 4, modified combination n = 6, psi = 1."""
     return dict(name=f"batch4_{count}x_n{n}_psi{psi}", problems=draw_instances(count, seed),
+                grid=combination(n, psi), steps=steps, richardson=False)
+
+
+def surrogate_instances(count: int, seed: int, d: int = 6) -> List[Problem]:
+    """Training / held-out instances of the surrogate: the batch distributions plus T ~ U[0.5,1.5]
+    and lambda ~ U[0.05,0.3], domain 4x the evaluation point."""
+    return [relative_domain(p) for p in draw_instances(count, seed, d=d, T_range=(0.5, 1.5),
+                                                        lam_range=(0.05, 0.3))]
+
+
+def workload_surrogate_labels(count: int, seed: int, n: int = 5, psi: int = 1, steps: int = 100) -> dict:
+    """Label generation for the surrogate: d = 6 modified combination n = 5, psi = 1, 100 steps."""
+    return dict(name=f"surrogate_d6_n{n}_psi{psi}_seed{seed}", problems=surrogate_instances(count, seed),
                 grid=combination(n, psi), steps=steps, richardson=False)
 
 

@@ -1,0 +1,228 @@
+"""Learned pricing surrogate on top of the solver.
+
+A small network maps the eight instance parameters (beta, sigma, phi, F0, V0, K, T, lambda) to a
+price and an estimate of its own error; it is trained on prices the solver computes, and requests
+whose estimated relative error exceeds the caller's tolerance, or that fall outside the training
+box, are priced by the solver instead.  The network runs in libamfrw (BF16 MFMA kernels, FP32
+accumulation); this module marshals arguments and orchestrates training and fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import time
+from typing import List, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from . import inputs as I
+from .solver import Plan, _stream
+
+
+def _mlp_lib():
+    lib = L.lib()
+    if not getattr(lib, "_mlp_ready", False):
+        vp, st = C.c_void_p, C.c_int32
+        lib.amf_mlp_last_error.restype = C.c_char_p
+        lib.amf_mlp_create.restype = st
+        lib.amf_mlp_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                       C.POINTER(vp)]
+        lib.amf_mlp_info_get.restype = st
+        lib.amf_mlp_info_get.argtypes = [vp, C.POINTER(MlpInfo)]
+        lib.amf_mlp_bind.restype = st
+        lib.amf_mlp_bind.argtypes = [vp, vp, C.c_uint64, vp]
+        lib.amf_mlp_set_normalization.restype = st
+        fp = C.POINTER(C.c_float)
+        lib.amf_mlp_set_normalization.argtypes = [vp, fp, fp, fp, fp, vp]
+        lib.amf_mlp_params.restype = st
+        lib.amf_mlp_params.argtypes = [vp, vp, C.c_int32, vp]
+        lib.amf_mlp_grads.restype = st
+        lib.amf_mlp_grads.argtypes = [vp, vp, vp]
+        lib.amf_mlp_forward.restype = st
+        lib.amf_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp]
+        lib.amf_mlp_backward.restype = st
+        lib.amf_mlp_backward.argtypes = [vp, vp, C.c_int32, vp]
+        lib.amf_mlp_train_step.restype = st
+        lib.amf_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.c_float, vp, vp]
+        lib.amf_mlp_destroy.restype = None
+        lib.amf_mlp_destroy.argtypes = [vp]
+        lib._mlp_ready = True
+    return lib
+
+
+class MlpInfo(C.Structure):
+    _fields_ = [("n_params", C.c_int64), ("workspace_bytes", C.c_uint64), ("n_in", C.c_int32),
+                ("width", C.c_int32), ("depth", C.c_int32), ("n_out", C.c_int32), ("max_batch", C.c_int32),
+                ("layers", C.c_int32), ("layer_rows", C.c_int32 * 8), ("layer_cols", C.c_int32 * 8),
+                ("layer_w_offset", C.c_int64 * 8), ("layer_b_offset", C.c_int64 * 8)]
+
+
+def _check(st):
+    if st != L.OK:
+        raise L.AmfError(st, _mlp_lib().amf_mlp_last_error().decode())
+
+
+FEATURES = ["beta", "sigma", "phi", "F0", "V0", "K", "T", "lambda"]
+
+
+class Mlp:
+    """The network: n_in -> width x depth (SiLU) -> (price, log error), on `device`."""
+
+    def __init__(self, n_in=8, width=256, depth=3, max_batch=8192, seed=1, device="cuda:0"):
+        lib = _mlp_lib()
+        h = C.c_void_p()
+        _check(lib.amf_mlp_create(n_in, width, depth, 2, max_batch, seed, C.byref(h)))
+        self._h = h
+        self.info = MlpInfo()
+        _check(lib.amf_mlp_info_get(h, C.byref(self.info)))
+        self.device = torch.device(device)
+        self.ws = torch.empty(int(self.info.workspace_bytes) + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        off = (-base) % 256
+        _check(lib.amf_mlp_bind(h, C.c_void_p(base + off), int(self.info.workspace_bytes), _stream()))
+        self.n_in = n_in
+        self.max_batch = max_batch
+        self.norm = None
+
+    def layout(self):
+        i = self.info
+        n = i.layers
+        return ([i.layer_rows[l] for l in range(n)], [i.layer_cols[l] for l in range(n)],
+                [i.layer_w_offset[l] for l in range(n)], [i.layer_b_offset[l] for l in range(n)])
+
+    def set_normalization(self, in_mean, in_std, out_mean, out_std):
+        f = lambda a: (C.c_float * len(a))(*[float(v) for v in a])
+        self.norm = (np.asarray(in_mean, np.float32), np.asarray(in_std, np.float32), float(out_mean), float(out_std))
+        _check(_mlp_lib().amf_mlp_set_normalization(self._h, f(in_mean), f(in_std), f([out_mean]), f([out_std]),
+                                                    _stream()))
+
+    def params(self) -> torch.Tensor:
+        out = torch.empty(int(self.info.n_params), dtype=torch.float32, device=self.device)
+        _check(_mlp_lib().amf_mlp_params(self._h, C.c_void_p(out.data_ptr()), 0, _stream()))
+        return out
+
+    def load_params(self, p: torch.Tensor):
+        p = p.to(device=self.device, dtype=torch.float32).contiguous()
+        _check(_mlp_lib().amf_mlp_params(self._h, C.c_void_p(p.data_ptr()), 1, _stream()))
+
+    def grads(self) -> torch.Tensor:
+        out = torch.empty(int(self.info.n_params), dtype=torch.float32, device=self.device)
+        _check(_mlp_lib().amf_mlp_grads(self._h, C.c_void_p(out.data_ptr()), _stream()))
+        return out
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """x: [B, n_in] FP32 raw features -> [B, 2] (price, estimated relative error)."""
+        x = x.to(device=self.device, dtype=torch.float32).contiguous()
+        B = x.shape[0]
+        out = torch.empty(B, 2, dtype=torch.float32, device=self.device)
+        for s in range(0, B, self.max_batch):
+            e = min(B, s + self.max_batch)
+            _check(_mlp_lib().amf_mlp_forward(self._h, C.c_void_p(x[s:e].data_ptr()), e - s,
+                                              C.c_void_p(out[s:e].data_ptr()), _stream()))
+        return out
+
+    def backward(self, dy: torch.Tensor):
+        dy = dy.to(device=self.device, dtype=torch.float32).contiguous()
+        _check(_mlp_lib().amf_mlp_backward(self._h, C.c_void_p(dy.data_ptr()), dy.shape[0], _stream()))
+
+    def train_step(self, x: torch.Tensor, t: torch.Tensor, lr: float, err_weight: float = 0.1,
+                   loss: torch.Tensor | None = None):
+        _check(_mlp_lib().amf_mlp_train_step(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                             x.shape[0], float(lr), float(err_weight),
+                                             C.c_void_p(loss.data_ptr()) if loss is not None else None,
+                                             _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _mlp_lib().amf_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------------------------
+def solver_prices(problems: Sequence[I.Problem], grid, steps: int, precision: str = "fp32",
+                  chunk: int = 512, device: str = "cuda:0") -> np.ndarray:
+    """Prices of `problems` by the solver (batched plans of `chunk` instances, hipGraph replay)."""
+    out = []
+    for s in range(0, len(problems), chunk):
+        plan = Plan(problems[s:s + chunk], grid, steps, precision=precision, device=device)
+        out.append(plan.price().cpu().numpy())
+        del plan
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def features(problems: Sequence[I.Problem]) -> np.ndarray:
+    return np.asarray([I.surrogate_features(p) for p in problems], dtype=np.float32)
+
+
+class Surrogate:
+    """Trained network plus the box it was trained on; `price` serves requests with fallback."""
+
+    def __init__(self, mlp: Mlp, box_lo: np.ndarray, box_hi: np.ndarray, grid, steps: int, calib: float = 1.0):
+        self.mlp, self.box_lo, self.box_hi, self.grid, self.steps = mlp, box_lo, box_hi, grid, steps
+        self.calib = calib
+
+    def calibrate(self, x: np.ndarray, y: np.ndarray, q: float = 0.95) -> float:
+        """Scale the error estimate so that a fraction q of the calibration residuals (data not
+        used for training) lie below it: calib = q-quantile of |actual rel. error| / estimate."""
+        p, err = self.predict(x)
+        ratio = (np.abs(p - y) / np.abs(y)) / np.maximum(err, 1e-30)
+        self.calib = float(np.quantile(ratio, q))
+        return self.calib
+
+    @staticmethod
+    def train(x: np.ndarray, y: np.ndarray, grid, steps: int, epochs: int = 300, batch: int = 1024,
+              lr: float = 2e-3, seed: int = 1, width: int = 256, depth: int = 3, err_weight: float = 0.1,
+              device: str = "cuda:0", log=None) -> "Surrogate":
+        mlp = Mlp(n_in=x.shape[1], width=width, depth=depth, max_batch=max(batch, 8192), seed=seed,
+                  device=device)
+        mlp.set_normalization(x.mean(axis=0), x.std(axis=0) + 1e-12, float(y.mean()), float(y.std()))
+        xt = torch.tensor(x, dtype=torch.float32, device=device)
+        yt = torch.tensor(y, dtype=torch.float32, device=device)
+        n = x.shape[0]
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        loss = torch.zeros(1, dtype=torch.float32, device=device)
+        steps_total = epochs * max(1, n // batch)
+        k = 0
+        for ep in range(epochs):
+            perm = torch.randperm(n, generator=g).to(device)
+            for s in range(0, n - batch + 1, batch):
+                idx = perm[s:s + batch]
+                xb = xt[idx].contiguous()
+                yb = yt[idx].contiguous()
+                # cosine decay of the learning rate
+                cur = lr * 0.5 * (1.0 + math.cos(math.pi * k / steps_total))
+                mlp.train_step(xb, yb, max(cur, lr * 1e-3), err_weight, loss)
+                k += 1
+            if log is not None and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
+                log("epoch %d loss %.3e" % (ep, loss.item() / batch))
+        return Surrogate(mlp, x.min(axis=0), x.max(axis=0), grid, steps)
+
+    def predict(self, x: np.ndarray):
+        """(price, estimated relative error before calibration) from the network."""
+        out = self.mlp.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
+        return out[:, 0].astype(np.float64), out[:, 1].astype(np.float64)
+
+    def price(self, problems: Sequence[I.Problem], tol: float = 1e-4, precision: str = "fp32"):
+        """Prices with fallback: the network's price where its estimated relative error is at most
+        `tol` and the request lies inside the training box, else the solver's.  Returns (prices,
+        used_solver mask, seconds spent in the network, seconds spent in the solver)."""
+        x = features(problems)
+        t0 = time.perf_counter()
+        p, err = self.predict(x)
+        t1 = time.perf_counter()
+        inside = np.all((x >= self.box_lo) & (x <= self.box_hi), axis=1)
+        use_solver = (~inside) | (err * self.calib > tol) | ~np.isfinite(p)
+        idx = np.nonzero(use_solver)[0]
+        t2 = time.perf_counter()
+        if len(idx):
+            p[idx] = solver_prices([problems[i] for i in idx], self.grid, self.steps, precision)
+        t3 = time.perf_counter()
+        return p, use_solver, t1 - t0, t3 - t2

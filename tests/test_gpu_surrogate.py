@@ -1,0 +1,102 @@
+"""GPU parity of the surrogate network (BF16 MFMA kernels) against the FP64 CPU reference with the
+same BF16 rounding points, training progress, and the surrogate-with-fallback against the solver."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp as M
+from paper_2408_00559_amd import inputs as I
+from paper_2408_00559_amd import surrogate as S
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _setup(seed=3, B=200):
+    net = S.Mlp(n_in=8, width=256, depth=3, max_batch=1024, seed=seed, device=DEV)
+    rng = np.random.default_rng(seed)
+    mean = rng.normal(size=8).astype(np.float32)
+    std = rng.uniform(0.5, 2.0, 8).astype(np.float32)
+    net.set_normalization(mean, std, 0.02, 0.01)
+    x = (mean + std * rng.normal(size=(B, 8))).astype(np.float32)
+    lay = M.Layout(*net.layout())
+    return net, lay, x, mean, std
+
+
+def test_forward_matches_reference():
+    net, lay, x, mean, std = _setup()
+    out = net.forward(torch.tensor(x)).cpu().numpy()
+    p = net.params().cpu().numpy().astype(np.float64)
+    y, _ = M.forward(lay, p, x, mean, std, bf16=True)
+    price = y[:, 0] * 0.01 + 0.02
+    err = np.exp(y[:, 1]) * 0.01 / np.abs(price)
+    assert np.max(np.abs(out[:, 0] - price)) < 2e-3 * np.max(np.abs(price))
+    assert np.max(np.abs(np.log(out[:, 1]) - np.log(err))) < 2e-2
+
+
+def test_gradients_match_reference():
+    net, lay, x, mean, std = _setup(seed=5, B=96)
+    rng = np.random.default_rng(7)
+    dy = rng.normal(size=(x.shape[0], 2)).astype(np.float32)
+    net.forward(torch.tensor(x))
+    net.backward(torch.tensor(dy))
+    g = net.grads().cpu().numpy().astype(np.float64)
+    p = net.params().cpu().numpy().astype(np.float64)
+    y, cache = M.forward(lay, p, x, mean, std, bf16=True)
+    gr = M.backward(lay, cache, dy, bf16=True)
+    for l in range(lay.layers):
+        for off, size in ((lay.w_off[l], lay.rows[l] * lay.cols[l]), (lay.b_off[l], lay.rows[l])):
+            a, b = g[off:off + size], gr[off:off + size]
+            scale = np.max(np.abs(b)) + 1e-30
+            assert np.max(np.abs(a - b)) < 3e-2 * scale, (l, np.max(np.abs(a - b)) / scale)
+
+
+def test_training_reduces_loss():
+    net = S.Mlp(n_in=8, width=256, depth=3, max_batch=2048, seed=11, device=DEV)
+    rng = np.random.default_rng(11)
+    x = rng.uniform(-1, 1, (4096, 8)).astype(np.float32)
+    t = (np.sin(x[:, 0] * 2) + x[:, 1] * x[:, 2] + 0.5 * x[:, 3] ** 2).astype(np.float32)
+    net.set_normalization(np.zeros(8), np.ones(8), float(t.mean()), float(t.std()))
+    xt = torch.tensor(x, device=DEV)
+    tt = torch.tensor(t, device=DEV)
+    loss = torch.zeros(1, device=DEV)
+    first = None
+    for k in range(2000):
+        i = k % 4
+        net.train_step(xt[i * 1024:(i + 1) * 1024].contiguous(), tt[i * 1024:(i + 1) * 1024].contiguous(),
+                       2e-3 if k < 1500 else 2e-4, 0.0, loss)
+        if first is None:
+            first = loss.item()
+    pred = net.forward(xt).cpu().numpy()[:, 0]
+    rmse = float(np.sqrt(np.mean((pred - t) ** 2)))
+    assert loss.item() < 0.05 * first and rmse < 0.05 * t.std(), (first, loss.item(), rmse)
+
+
+def test_surrogate_gain_with_fallback():
+    """Trained on solver prices (d = 4, n = 4, psi = 1, 20 steps), the surrogate serves held-out
+    requests much faster than the solver; requests above the error tolerance go to the solver, so
+    every returned price is either the solver's or within the tolerance of it."""
+    grid, steps = I.combination(4, 1), 20
+    train = I.draw_instances(3072, seed=50, d=4, T_range=(0.5, 1.5), lam_range=(0.05, 0.3))
+    cal = I.draw_instances(512, seed=52, d=4, T_range=(0.5, 1.5), lam_range=(0.05, 0.3))
+    held = I.draw_instances(512, seed=51, d=4, T_range=(0.5, 1.5), lam_range=(0.05, 0.3))
+    ytr = S.solver_prices(train, grid, steps)
+    sur = S.Surrogate.train(S.features(train), ytr, grid, steps, epochs=300, batch=512, device=DEV)
+    sur.calibrate(S.features(cal), S.solver_prices(cal, grid, steps))
+    torch.cuda.synchronize()
+    import time
+    t0 = time.perf_counter()
+    yref = S.solver_prices(held, grid, steps)
+    t_solver = time.perf_counter() - t0
+    tol = 3e-2
+    p, used, t_net, t_fb = sur.price(held, tol=tol)
+    rel = np.abs(p - yref) / np.abs(yref)
+    served = ~used
+    assert served.sum() > 0
+    # the network alone is far cheaper than the solver on the same requests
+    assert t_net < 0.2 * t_solver, (t_net, t_solver)
+    # fallback prices are the solver's
+    assert np.max(rel[used], initial=0.0) < 1e-6
+    # the calibrated error estimate is an honest filter: served prices meet the tolerance up to the
+    # calibration quantile
+    assert np.quantile(rel[served], 0.9) < tol, np.quantile(rel[served], 0.9)
