@@ -43,9 +43,10 @@ def kernel_class_of(name: str):
     if "k_stencil<" in name:
         op = name.split("k_stencil<", 1)[1].split(">", 1)[0].split(",")[-1].strip()
         return {"0": "operator", "1": "operator", "2": "stage1", "3": "stage2", "4": "refine"}[op]
-    for k in ("k_node", "k_unit_values", "k_combine"):
+    for k in ("k_node", "k_unit_values", "k_combine", "k_resident"):
         if k in name:
-            return {"k_node": "init", "k_unit_values": "unit_values", "k_combine": "combine"}[k]
+            return {"k_node": "init", "k_unit_values": "unit_values", "k_combine": "combine",
+                    "k_resident": "resident"}[k]
     assert L.K_NAMES
     return None
 

@@ -191,12 +191,18 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
  *   stencil_nodes: consecutive axis-1 nodes evaluated per thread by the time-loop operator
  *                  (1, 2 or 4; at most max_stencil_nodes = min(4, smallest M_1 of the plan)).
  *   xcd_remap:     1 = assign each XCD a contiguous share of the blocks (its own L2), 0 = off.
+ *   resident:      1 = unit-resident schedule: one workgroup per component grid runs all time steps
+ *                  of a call with the grid's vectors in LDS (only when resident_available, i.e.
+ *                  every grid has at most 2048 points in FP32 or 1024 in FP64); 0 = streaming
+ *                  schedule: one launch per operator / axis over all grids.
  * amf_schedule_set may be called at any time between enqueued calls; AMF_E_INVALID otherwise. */
 typedef struct {
     uint32_t struct_size;
     int32_t stencil_nodes;
     int32_t xcd_remap;
     int32_t max_stencil_nodes;   /* read-only: filled by amf_schedule_get */
+    int32_t resident;
+    int32_t resident_available;  /* read-only: filled by amf_schedule_get */
 } amf_schedule;
 
 amf_status amf_schedule_get(const amf_plan* plan, amf_schedule* out);
@@ -221,7 +227,8 @@ typedef enum {
     AMF_K_SWEEP_UPDATE_LONG = 10, /* ... longer lines                                         */
     AMF_K_UNIT_VALUES = 11,     /* interpolation at x_eval                                    */
     AMF_K_COMBINE = 12,         /* FP64 combination                                           */
-    AMF_K_COUNT = 13
+    AMF_K_RESIDENT = 13,        /* unit-resident time loop (all stages and solves in LDS)     */
+    AMF_K_COUNT = 14
 } amf_kernel_class;
 
 typedef struct {
@@ -263,9 +270,12 @@ amf_status amf_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_
 amf_status amf_mlp_info_get(const amf_mlp* mlp, amf_mlp_info* out);
 /* Bind the workspace and upload the initial parameters (synchronises the stream). */
 amf_status amf_mlp_bind(amf_mlp* mlp, void* d_workspace, uint64_t bytes, void* stream);
-/* Host arrays: feature means and standard deviations (n_in each), price mean and scale (1 each). */
+/* Host arrays: feature means and standard deviations (n_in each), target mean and scale (1 each).
+ * out_log = 1: the network models log(price) (mean and scale of log prices; targets must be > 0),
+ * so its residual is a relative error; out_log = 0: it models the price itself. */
 amf_status amf_mlp_set_normalization(amf_mlp* mlp, const float* in_mean, const float* in_std,
-                                     const float* out_mean, const float* out_std, void* stream);
+                                     const float* out_mean, const float* out_std, int32_t out_log,
+                                     void* stream);
 /* direction 0: copy the FP32 master parameters to d_params; 1: load them from d_params (device). */
 amf_status amf_mlp_params(amf_mlp* mlp, float* d_params, int32_t direction, void* stream);
 /* Copy the gradient of the last backward pass / training step (same layout as the parameters). */
@@ -278,7 +288,7 @@ amf_status amf_mlp_forward(amf_mlp* mlp, const float* d_x, int32_t batch, float*
 amf_status amf_mlp_backward(amf_mlp* mlp, const float* d_dy, int32_t batch, void* stream);
 /* One Adam step (beta 0.9/0.999, eps 1e-8) on the loss
  *   mean_b (y0 - t_b)^2 + err_weight (y1 - log(|y0 - t_b| + 1e-6))^2,  t_b the normalised target price;
- * the residual in the second term is held constant.  d_loss (device, optional) receives the batch
+ * the residual in the second term is held constant, t_b the normalised target (or log target).  d_loss (device, optional) receives the batch
  * sum before the division by the batch size. */
 amf_status amf_mlp_train_step(amf_mlp* mlp, const float* d_x, const float* d_target, int32_t batch,
                               float lr, float err_weight, float* d_loss, void* stream);

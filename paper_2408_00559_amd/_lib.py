@@ -48,7 +48,7 @@ class AmfPlanInfo(C.Structure):
 
 class AmfSchedule(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("stencil_nodes", C.c_int32), ("xcd_remap", C.c_int32),
-                ("max_stencil_nodes", C.c_int32)]
+                ("max_stencil_nodes", C.c_int32), ("resident", C.c_int32), ("resident_available", C.c_int32)]
 
 
 class AmfKernelStat(C.Structure):
@@ -58,7 +58,7 @@ class AmfKernelStat(C.Structure):
 
 K_NAMES = ["init", "operator", "stage1", "stage2", "refine", "sweep_contig", "sweep_contig_long",
            "sweep_strided", "sweep_strided_long", "sweep_update", "sweep_update_long", "unit_values",
-           "combine"]
+           "combine", "resident"]
 # device kernel symbol of each class (template arguments omitted)
 K_SYMBOLS = {"init": "k_node", "operator": "k_stencil<OP_F_PAYOFF>", "stage1": "k_stencil<OP_STAGE1>",
              "stage2": "k_stencil<OP_STAGE2>", "refine": "k_stencil<OP_REFINE>",
@@ -67,7 +67,7 @@ K_SYMBOLS = {"init": "k_node", "operator": "k_stencil<OP_F_PAYOFF>", "stage1": "
              "sweep_strided_long": "k_sweep_strided<EPI_STORE, true>",
              "sweep_update": "k_sweep_strided<EPI_UPDATE, false>",
              "sweep_update_long": "k_sweep_strided<EPI_UPDATE, true>",
-             "unit_values": "k_unit_values", "combine": "k_combine"}
+             "unit_values": "k_unit_values", "combine": "k_combine", "resident": "k_resident"}
 K_COUNT = len(K_NAMES)
 
 
@@ -144,4 +144,7 @@ def check(status: int):
 EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_plan_create",
             "amf_plan_info_get", "amf_unit_info", "amf_plan_bind", "amf_init", "amf_time_step",
             "amf_solve", "amf_graph_enable", "amf_unit_values", "amf_combine", "amf_state_read", "amf_apply_operator",
-            "amf_axis_solve", "amf_schedule_get", "amf_schedule_set", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy"]
+            "amf_axis_solve", "amf_schedule_get", "amf_schedule_set", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy",
+            "amf_mlp_last_error", "amf_mlp_create", "amf_mlp_info_get", "amf_mlp_bind",
+            "amf_mlp_set_normalization", "amf_mlp_params", "amf_mlp_grads", "amf_mlp_forward",
+            "amf_mlp_backward", "amf_mlp_train_step", "amf_mlp_destroy"]

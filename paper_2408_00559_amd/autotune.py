@@ -26,9 +26,12 @@ def signature(plan) -> str:
 
 
 def candidates(plan):
-    mx = plan.schedule()["max_stencil_nodes"]
-    nodes = [r for r in (1, 2, 4) if r <= mx]
-    return [dict(stencil_nodes=r, xcd_remap=x) for r, x in itertools.product(nodes, (1, 0))]
+    sc = plan.schedule()
+    nodes = [r for r in (1, 2, 4) if r <= sc["max_stencil_nodes"]]
+    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0) for r, x in itertools.product(nodes, (1, 0))]
+    if sc["resident_available"]:
+        out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1))
+    return out
 
 
 def _time(plan, steps: int, reps: int) -> float:

@@ -49,6 +49,8 @@ struct amf_plan {
     std::vector<int32_t> blk_unit;
     std::vector<int32_t> blk_unit_r[3];    // node blocks of NODE_BLOCK * {1, 2, 4} nodes
     int stencil_r = 1, min_m0 = 1, xcd = 1;
+    bool res_ok = false;                   // every unit fits the unit-resident schedule
+    int resident = 0, res_lds_len = 0;
     std::vector<int32_t> ax_units[MAXD];
     std::vector<int64_t> ax_line_off[MAXD];
     std::vector<SweepBlk> ax_blk[MAXD];
@@ -434,6 +436,10 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         int min_m0 = 1 << 16;
         for (int u = 0; u < P->n_units; ++u) min_m0 = std::min(min_m0, 1 << P->units[u].lv[0]);
         P->min_m0 = min_m0;
+        int max_lsum = 0;
+        for (int u = 0; u < P->n_units; ++u) max_lsum = std::max(max_lsum, (int)P->units[u].lsum);
+        P->res_ok = max_lsum <= (precision == AMF_FP64 ? RES_MAX_LSUM_F64 : RES_MAX_LSUM_F32);
+        P->res_lds_len = (1 << max_lsum) + ((1 << max_lsum) >> 4);
         const int rmax = precision == AMF_FP64 ? STENCIL_R_F64 : STENCIL_R_F32;
         P->stencil_r = std::min(rmax, min_m0) >= 4 ? 4 : (std::min(rmax, min_m0) >= 2 ? 2 : 1);
         // per axis: units ordered by M_axis, line offsets, blocks that never mix line lengths
@@ -700,6 +706,33 @@ hipError_t run_unit_values(amf_plan* P, double* vals, hipStream_t s)
                  [&] { return launch_unit_values(P->dev, P->prec, P->vec(V_W), vals, s); });
 }
 
+amf_status one_step(amf_plan* P, int run, hipStream_t s);
+
+// n AMFR-W steps on every unit: one unit-resident launch, or n streaming steps.
+amf_status advance(amf_plan* P, int run, int n, hipStream_t s)
+{
+    if (P->resident) {
+        ResArgs a{};
+        a.W = P->vec(V_W);
+        a.cG = P->vec(V_G);
+        a.run = run;
+        a.nsteps = n;
+        a.a21 = P->sch.a[1 * AMF_MAX_STAGES + 0];
+        a.q21 = P->sch.q[1 * AMF_MAX_STAGES + 0];
+        a.b1 = P->sch.b[0];
+        a.b2 = P->sch.b[1];
+        a.lds_len = P->res_lds_len;
+        hipError_t e = timed(P, AMF_K_RESIDENT, (2.0 + 2.0 * n) * P->vbytes(), s,
+                             [&] { return launch_resident(P->dev, P->prec, a, s); });
+        return e == hipSuccess ? AMF_OK : hip_fail(e, "resident");
+    }
+    for (int i = 0; i < n; ++i) {
+        amf_status st = one_step(P, run, s);
+        if (st) return st;
+    }
+    return AMF_OK;
+}
+
 // One AMFR-W step (eq amfrw) of the 2-stage scheme on every unit.  run selects dt (0: coarse,
 // 1: fine half step of the Richardson pair).
 amf_status one_step(amf_plan* P, int run, hipStream_t s)
@@ -786,9 +819,7 @@ amf_status amf_time_step(amf_plan* P, int32_t n, void* stream)
     if (st) return st;
     if (!P->initialised) return fail(AMF_E_STATE, "amf_init has not been called");
     if (n < 0) return fail(AMF_E_INVALID, "n must be >= 0");
-    for (int i = 0; i < n; ++i)
-        if ((st = one_step(P, 0, (hipStream_t)stream))) return st;
-    return AMF_OK;
+    return advance(P, 0, n, (hipStream_t)stream);
 }
 
 namespace {
@@ -799,15 +830,13 @@ amf_status solve_body(amf_plan* P, hipStream_t s)
     amf_status st;
     hipError_t e = run_init(P, s);
     if (e != hipSuccess) return hip_fail(e, "init");
-    for (int i = 0; i < P->steps; ++i)
-        if ((st = one_step(P, 0, s))) return st;
+    if ((st = advance(P, 0, P->steps, s))) return st;
     if (P->richardson) {
         e = run_unit_values(P, (double*)(P->ws + P->off_valsc), s);
         if (e != hipSuccess) return hip_fail(e, "unit values");
         if ((e = timed(P, AMF_K_INIT, P->vbytes(), s, [&] { return launch_fill_zero(P->dev, P->prec, P->vec(V_W), s); })) != hipSuccess)
             return hip_fail(e, "init");
-        for (int i = 0; i < 2 * P->steps; ++i)
-            if ((st = one_step(P, 1, s))) return st;
+        if ((st = advance(P, 1, 2 * P->steps, s))) return st;
     }
     return AMF_OK;
 }
@@ -943,6 +972,8 @@ amf_status amf_schedule_get(const amf_plan* P, amf_schedule* out)
     out->stencil_nodes = P->stencil_r;
     out->xcd_remap = P->xcd;
     out->max_stencil_nodes = std::min(4, P->min_m0);
+    out->resident = P->resident;
+    out->resident_available = P->res_ok ? 1 : 0;
     return AMF_OK;
 }
 
@@ -953,7 +984,10 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (r != 1 && r != 2 && r != 4) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2 or 4");
     if (r > P->min_m0) return fail(AMF_E_INVALID, "stencil_nodes exceeds the smallest axis-1 line");
     if (sc->xcd_remap != 0 && sc->xcd_remap != 1) return fail(AMF_E_INVALID, "xcd_remap must be 0 or 1");
-    if (r != P->stencil_r || sc->xcd_remap != P->xcd) P->drop_graph();
+    if (sc->resident != 0 && sc->resident != 1) return fail(AMF_E_INVALID, "resident must be 0 or 1");
+    if (sc->resident && !P->res_ok) return fail(AMF_E_INVALID, "a unit exceeds the unit-resident size limit");
+    if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident) P->drop_graph();
+    P->resident = sc->resident;
     P->stencil_r = r;
     P->xcd = sc->xcd_remap;
     P->dev.stencil_r = r;

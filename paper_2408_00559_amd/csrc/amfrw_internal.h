@@ -122,7 +122,21 @@ struct SweepArgs {
     int run;              // 0 coarse, 1 fine (Richardson)
 };
 
+// Unit-resident schedule: one workgroup of RES_BLOCK threads per unit, the whole time loop in LDS.
+constexpr int RES_BLOCK = 128;
+constexpr int RES_MAX_LSUM_F32 = 11;   // units up to 2048 points (5 padded FP32 vectors: 43.5 KB)
+constexpr int RES_MAX_LSUM_F64 = 10;   // units up to 1024 points (5 padded FP64 vectors: 43.5 KB)
+
+struct ResArgs {
+    void* W;              // solution W (global), read at entry and written at exit
+    const void* cG;       // F(g) (global)
+    int run, nsteps;
+    double a21, q21, b1, b2;
+    int lds_len;          // padded elements per LDS vector (li of the largest unit)
+};
+
 // Kernel launchers (amfrw_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_resident(const DevPlan& P, int prec, const ResArgs& a, hipStream_t s);
 hipError_t launch_payoff(const DevPlan& P, int prec, void* Y, hipStream_t s);
 hipError_t launch_fill_zero(const DevPlan& P, int prec, void* Y, hipStream_t s);
 hipError_t launch_state_read(const DevPlan& P, int prec, const void* W, void* Y, hipStream_t s);

@@ -533,15 +533,12 @@ __device__ __forceinline__ Contig contig_geom(const DevPlan& P, const UnitDev& U
     return C;
 }
 
-// Short contiguous line: one thread, Thomas with the line in VGPRs.
+// Short contiguous line: one thread, Thomas with the line in VGPRs.  in/out: the line's M
+// consecutive values (may alias), td: its tdiff factors, cm = V^2 of the line.
 template <typename T, int LM>
-__device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Contig& L, T nudt)
+__device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm, T nudt)
 {
     constexpr int M = 1 << LM;
-    const T* in = (const T*)A.in + L.base;
-    T* out = (T*)A.out + L.base;
-    const T* td = (const T*)L.tdiff;
-    const T cm = (T)L.vsq;
     T g[M], cp[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) g[r] = in[r];
@@ -561,20 +558,22 @@ __device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Conti
     for (int r = 0; r < M; ++r) out[r] = g[r];
 }
 
+template <typename T, int LM>
+__device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Contig& L, T nudt)
+{
+    reg_solve<T, LM>((const T*)A.in + L.base, (T*)A.out + L.base, (const T*)L.tdiff, (T)L.vsq, nudt);
+}
+
 // Long contiguous line: SP = M/SEG lanes, each owning SEG consecutive rows.  Each lane eliminates
 // its first SEG-1 rows in terms of z_{p-1} (last row of the previous segment) and z_p (its own last
 // row): x_k = y_k + v_k z_{p-1} + w_k z_p.  Substituting into the segment-closing rows leaves a
 // tridiagonal system in z_0..z_{SP-1}, solved by parallel cyclic reduction across the SP lanes with
 // wavefront shuffles; the lanes then reconstruct their rows.  Diagonally dominant: no pivoting.
+// in/out: the lane's SEG rows (contiguous), td: their tdiff factors, cm = V^2 of the line.
 template <typename T, int SP>
-__device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Contig& L, T nudt, int p)
+__device__ __forceinline__ void part_solve(const T* in, T* out, const T* td, T cm, T nudt, int p)
 {
     constexpr int S = SEG;
-    const int r0 = p * S;
-    const T* in = (const T*)A.in + L.base + r0;
-    T* out = (T*)A.out + L.base + r0;
-    const T* td = (const T*)L.tdiff + r0;
-    const T cm = (T)L.vsq;
     const bool first = (p == 0), last = (p == SP - 1);
     T g[S], cp[S - 1], v[S - 1], w[S - 1];
 #pragma unroll
@@ -643,6 +642,14 @@ __device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Cont
     out[S - 1] = z;
 }
 
+template <typename T, int SP>
+__device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Contig& L, T nudt, int p)
+{
+    const int r0 = p * SEG;
+    part_solve<T, SP>((const T*)A.in + L.base + r0, (T*)A.out + L.base + r0, (const T*)L.tdiff + r0,
+                      (T)L.vsq, nudt, p);
+}
+
 template <typename T, bool LONG>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArgs A, int64_t blk0)
 {
@@ -678,6 +685,231 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArg
         default: break;   // longer lines are rejected at plan creation
         }
     }
+}
+
+// ------------------------------------------------------------------------------------------------
+// Unit-resident schedule: one workgroup per unit advances it by n AMFR-W steps with W, K1, two work
+// vectors and the Thomas scratch in LDS; only W (in and out) and F(g) (read per stage) touch
+// global memory.  LDS arrays are padded by one element per 16 (li) so that lanes walking lines of
+// any axis hit distinct banks.
+__device__ __forceinline__ int li(int n) { return n + (n >> 4); }
+
+template <int D>
+struct ResGeom {
+    int M[D], S[D];   // extents and index shifts (E_i = 1 << S_i)
+    int Pn, SV, MV;
+};
+
+// Zero-face Sketch-1 operator on LDS vectors, fused with the stage combination OP.
+template <typename T, int D, int OP>
+__device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const UnitDev& U, const T* tab, const T* cst,
+                                            T sc, T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
+{
+    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) {
+        int j[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) j[i] = ((n >> G.S[i]) & (G.M[i] - 1)) + 1;
+        auto X = [&](int idx) -> T {
+            if constexpr (OP == OP_STAGE2) return X0[li(idx)] + av * X1[li(idx)];
+            else return X0[li(idx)];
+        };
+        auto nb2 = [&](int i, int si, int k, int sk) -> T {
+            if ((si < 0 && j[i] == 1) || (sk < 0 && j[k] == 1)) return T(0);
+            return X(n + si * (1 << G.S[i]) + sk * (1 << G.S[k]));
+        };
+        const T c0 = X(n);
+        T xm[D], xp[D], tmix[D], tphi[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int E = 1 << G.S[i];
+            xm[i] = (j[i] == 1) ? T(0) : X(n - E);
+            xp[i] = (j[i] == G.M[i]) ? xm[i] : X(n + E);
+        }
+        const T* tV = tab + U.tab[D - 1];
+        const T vsq = tV[j[D - 1] - 1];
+        T acc = tV[G.MV] * (xp[D - 1] - T(2) * c0 + xm[D - 1]);
+        tmix[D - 1] = tV[G.MV + 1];
+        tphi[D - 1] = T(0);
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) {
+            const T* ti = tab + U.tab[i];
+            tmix[i] = ti[G.M[i] + j[i] - 1];
+            tphi[i] = ti[2 * G.M[i] + j[i] - 1];
+            acc += ti[j[i] - 1] * (xp[i] - T(2) * c0 + xm[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) {
+#pragma unroll
+            for (int k = i + 1; k < D; ++k) {
+                if (j[i] != G.M[i] && j[k] != G.M[k]) {
+                    const T xx = nb2(i, 1, k, 1) + nb2(i, -1, k, -1) - nb2(i, 1, k, -1) - nb2(i, -1, k, 1);
+                    const T cik = (k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i];
+                    acc += cik * tmix[i] * tmix[k] * xx;
+                }
+            }
+        }
+#pragma unroll
+        for (int i = 1; i < D - 1; ++i) {
+            if (j[i] != G.M[i]) {
+                T sacc = T(0);
+#pragma unroll
+                for (int jj = 1; jj <= i; ++jj) sacc += cst[CST_RHO + i * MAXD + jj] * tphi[jj];
+                acc += tmix[i] * sacc * (xp[i] - xm[i]);
+            }
+        }
+        const T F = vsq * acc;
+        const int ln = li(n);
+        if constexpr (OP == OP_STAGE1) Wout[ln] = sc * (F + cGg[n]);
+        else if constexpr (OP == OP_STAGE2) Wout[ln] = sc * (F + cGg[n]) + qv * X1[ln];
+        else Wout[ln] = T(2) * Wout[ln] - X0[ln] + sc * F;
+    }
+}
+
+// Axis-0 solves of every line of the unit (LDS in -> LDS out).
+template <typename T, int D>
+__device__ __forceinline__ void res_axis0(const ResGeom<D>& G, const UnitDev& U, const T* tab, T nudt,
+                                          const T* in, T* out)
+{
+    const int lm = U.lv[0];
+    const int lines = G.Pn >> lm;
+    const T* td = tab + U.tab[0];
+    const T* vs = tab + U.tab[D - 1];
+    if (lm <= CONTIG_REG_LM) {
+        for (int line = threadIdx.x; line < lines; line += RES_BLOCK) {
+            const int base = line << lm;
+            const T cm = vs[(base >> G.SV) & (G.MV - 1)];
+            const T* pi = in + li(base);
+            T* po = out + li(base);
+            switch (lm) {
+            case 0: reg_solve<T, 0>(pi, po, td, cm, nudt); break;
+            case 1: reg_solve<T, 1>(pi, po, td, cm, nudt); break;
+            case 2: reg_solve<T, 2>(pi, po, td, cm, nudt); break;
+            case 3: reg_solve<T, 3>(pi, po, td, cm, nudt); break;
+            default: reg_solve<T, 4>(pi, po, td, cm, nudt); break;
+            }
+        }
+    } else {
+        const int sp = (1 << lm) / SEG;
+        const int p = threadIdx.x & (sp - 1);
+        for (int line = threadIdx.x / sp; line < lines; line += RES_BLOCK / sp) {
+            const int base = line << lm;
+            const T cm = vs[(base >> G.SV) & (G.MV - 1)];
+            const int r0 = p * SEG;
+            const T* pi = in + li(base + r0);
+            T* po = out + li(base + r0);
+            switch (lm) {
+            case 5: part_solve<T, 2>(pi, po, td + r0, cm, nudt, p); break;
+            case 6: part_solve<T, 4>(pi, po, td + r0, cm, nudt, p); break;
+            case 7: part_solve<T, 8>(pi, po, td + r0, cm, nudt, p); break;
+            case 8: part_solve<T, 16>(pi, po, td + r0, cm, nudt, p); break;
+            case 9: part_solve<T, 32>(pi, po, td + r0, cm, nudt, p); break;
+            default: part_solve<T, 64>(pi, po, td + r0, cm, nudt, p); break;
+            }
+        }
+    }
+}
+
+// Solves along a strided axis (in place on `io`), Thomas with c' in the LDS scratch; with `upd`,
+// the result x updates W += b1 K1 + b2 x instead of being stored.
+template <typename T, int D>
+__device__ __forceinline__ void res_strided(const ResGeom<D>& G, const UnitDev& U, const T* tab, T nudt, int ax,
+                                            const T* in, T* io, T* sC, bool upd, T* sW, const T* sK, T b1, T b2)
+{
+    const int Mi = G.M[ax], Si = G.S[ax], E = 1 << Si;
+    const int lines = G.Pn / Mi;
+    const bool isV = ax == D - 1;
+    const T* td = tab + U.tab[ax];
+    const T* vs = tab + U.tab[D - 1];
+    const T tdV = vs[G.MV];
+    for (int line = threadIdx.x; line < lines; line += RES_BLOCK) {
+        const int lo = line & (E - 1), hi = line >> Si;
+        const int base = lo + (hi << (Si + U.lv[ax]));
+        const T cm = isV ? tdV : vs[(base >> G.SV) & (G.MV - 1)];
+        T cprev = T(0), dprev = T(0);
+        for (int r = 0; r < Mi; ++r) {
+            const int idx = li(base + r * E);
+            const T del = isV ? cm * vs[r] : td[r] * cm;
+            const T nd = nudt * del;
+            const T b = T(1) + T(2) * nd;
+            const T a = (r == 0) ? T(0) : ((r == Mi - 1) ? -T(2) * nd : -nd);
+            const T c = (r == Mi - 1) ? T(0) : -nd;
+            const T inv = T(1) / (b - a * cprev);
+            cprev = c * inv;
+            dprev = (in[idx] - a * dprev) * inv;
+            sC[idx] = cprev;
+            io[idx] = dprev;
+        }
+        T x = dprev;
+        for (int r = Mi - 1; r >= 0; --r) {
+            const int idx = li(base + r * E);
+            if (r < Mi - 1) x = io[idx] - sC[idx] * x;
+            if (upd) sW[idx] = sW[idx] + b1 * sK[idx] + b2 * x;
+            else io[idx] = x;
+        }
+    }
+}
+
+template <typename T, int D>
+__device__ __forceinline__ void res_chain(const ResGeom<D>& G, const UnitDev& U, const T* tab, T nudt,
+                                          const T* src, T* dst, T* sC, bool upd, T* sW, const T* sK, T b1, T b2)
+{
+    // every axis by one thread per line with c' in the LDS scratch (axis 0 reads src, then in place)
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) {
+        res_strided<T, D>(G, U, tab, nudt, ax, ax == 0 ? src : dst, dst, sC, upd && ax == D - 1, sW, sK, b1, b2);
+        __syncthreads();
+    }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
+{
+    extern __shared__ __align__(16) unsigned char res_smem[];
+    const UnitDev U = P.units[blockIdx.x];
+    ResGeom<D> G;
+    {
+        int sh = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            G.M[i] = 1 << U.lv[i];
+            G.S[i] = sh;
+            sh += U.lv[i];
+        }
+        G.Pn = 1 << U.lsum;
+        G.SV = G.S[D - 1];
+        G.MV = G.M[D - 1];
+    }
+    const int LP = A.lds_len;
+    T* sW = (T*)res_smem;
+    T* sK = sW + LP;
+    T* sA = sK + LP;
+    T* sB = sA + LP;
+    T* sC = sB + LP;
+    T* Wg = (T*)A.W + U.off;
+    const T* cGg = (const T*)A.cG + U.off;
+    const T* tab = (const T*)P.tab;
+    const T* cst = tab + P.probs[U.prob].cst;
+    const T dt = cst[CST_RUN + 3 * A.run], nudt = cst[CST_RUN + 3 * A.run + 1], thdt = cst[CST_RUN + 3 * A.run + 2];
+    const T a21 = (T)A.a21, q21 = (T)A.q21, b1 = (T)A.b1, b2 = (T)A.b2;
+    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) sW[li(n)] = Wg[n];
+    __syncthreads();
+    for (int st = 0; st < A.nsteps; ++st) {
+        // stage 1: K^(0) = dt F(Y); chain; refinement; chain -> K1
+        res_stencil<T, D, OP_STAGE1>(G, U, tab, cst, dt, T(0), T(0), sW, nullptr, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, U, tab, nudt, sA, sB, sC, false, sW, sK, b1, b2);
+        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, thdt, T(0), T(0), sB, nullptr, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, U, tab, nudt, sA, sK, sC, false, sW, sK, b1, b2);
+        // stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1; chain; refinement; chain ending in the update
+        res_stencil<T, D, OP_STAGE2>(G, U, tab, cst, dt, a21, q21, sW, sK, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, U, tab, nudt, sA, sB, sC, false, sW, sK, b1, b2);
+        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, thdt, T(0), T(0), sB, nullptr, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, U, tab, nudt, sA, sB, sC, true, sW, sK, b1, b2);
+    }
+    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) Wg[n] = sW[li(n)];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -853,6 +1085,28 @@ hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part,
         else sweep_part<float, true>(P, axis, epi, a, b0, nb, s);
     }
     return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t resident_t(const DevPlan& P, const ResArgs& a, hipStream_t s)
+{
+    dim3 g((unsigned)P.n_units), b(RES_BLOCK);
+    const size_t shm = (size_t)5 * a.lds_len * sizeof(T);
+    switch (P.d) {
+    case 2: hipLaunchKernelGGL((k_resident<T, 2>), g, b, shm, s, P, a); break;
+    case 3: hipLaunchKernelGGL((k_resident<T, 3>), g, b, shm, s, P, a); break;
+    case 4: hipLaunchKernelGGL((k_resident<T, 4>), g, b, shm, s, P, a); break;
+    case 5: hipLaunchKernelGGL((k_resident<T, 5>), g, b, shm, s, P, a); break;
+    case 6: hipLaunchKernelGGL((k_resident<T, 6>), g, b, shm, s, P, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_resident(const DevPlan& P, int prec, const ResArgs& a, hipStream_t s)
+{
+    if (P.n_units == 0 || a.nsteps <= 0) return hipSuccess;
+    return prec == 0 ? resident_t<double>(P, a, s) : resident_t<float>(P, a, s);
 }
 
 hipError_t launch_unit_values(const DevPlan& P, int prec, const void* W, double* vals, hipStream_t s)

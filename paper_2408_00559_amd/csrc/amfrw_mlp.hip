@@ -132,16 +132,19 @@ __global__ void k_input(const float* x, int batch, int nin, int kin, int bpad, c
     XT[(size_t)c * bpad + b] = h;
 }
 
-// Outputs: price = y0 * s0 + m0; error estimate (relative) = exp(y1) * s0 / |price|.
+// Outputs.  Linear target: price = y0 s0 + m0, relative error estimate exp(y1) s0 / |price|.
+// Logarithmic target (omean[8] != 0): price = exp(y0 s0 + m0), relative error estimate exp(y1) s0.
 __global__ void k_output(const float* Y, int batch, int ldy, const float* omean, const float* ostd,
                          float* out)
 {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= batch) return;
-    const float price = Y[(size_t)b * ldy + 0] * ostd[0] + omean[0];
-    const float err = __expf(Y[(size_t)b * ldy + 1]) * ostd[0] / fmaxf(fabsf(price), 1e-30f);
+    const bool lg = omean[8] != 0.0f;
+    const float u = Y[(size_t)b * ldy + 0] * ostd[0] + omean[0];
+    const float price = lg ? __expf(u) : u;
+    const float e = __expf(Y[(size_t)b * ldy + 1]) * ostd[0];
     out[2 * b + 0] = price;
-    out[2 * b + 1] = err;
+    out[2 * b + 1] = lg ? e : e / fmaxf(fabsf(price), 1e-30f);
 }
 
 // Loss and output gradient.  t = (target - m0)/s0, r = y0 - t;
@@ -155,7 +158,8 @@ __global__ void k_loss(const float* Y, const float* target, int batch, int bpad,
     if (b >= bpad) return;
     float g0 = 0.f, g1 = 0.f, l = 0.f;
     if (b < batch) {
-        const float t = (target[b] - omean[0]) / ostd[0];
+        const float tv = omean[8] != 0.0f ? __logf(target[b]) : target[b];
+        const float t = (tv - omean[0]) / ostd[0];
         const float y0 = Y[(size_t)b * ldy + 0], y1 = Y[(size_t)b * ldy + 1];
         const float rres = y0 - t;
         const float e = y1 - __logf(fabsf(rres) + 1e-6f);
@@ -540,14 +544,16 @@ amf_status amf_mlp_bind(amf_mlp* N, void* d_ws, uint64_t bytes, void* stream)
 }
 
 amf_status amf_mlp_set_normalization(amf_mlp* N, const float* in_mean, const float* in_std,
-                                     const float* out_mean, const float* out_std, void* stream)
+                                     const float* out_mean, const float* out_std, int32_t out_log,
+                                     void* stream)
 {
+    if (out_log != 0 && out_log != 1) return mfail(AMF_E_INVALID, "out_log must be 0 or 1");
     if (!N || !N->ws || !in_mean || !in_std || !out_mean || !out_std) return mfail(AMF_E_INVALID, "null argument");
     float normd[64];
     for (int i = 0; i < 16; ++i) {
         normd[i] = i < N->n_in ? in_mean[i] : 0.f;
         normd[16 + i] = i < N->n_in ? in_std[i] : 1.f;
-        normd[32 + i] = i < 1 ? out_mean[0] : 0.f;
+        normd[32 + i] = i < 1 ? out_mean[0] : (i == 8 ? (float)out_log : 0.f);
         normd[48 + i] = i < 1 ? out_std[0] : 1.f;
     }
     for (int i = 0; i < N->n_in; ++i)

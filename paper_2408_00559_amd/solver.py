@@ -172,14 +172,17 @@ class Plan:
         sc = L.AmfSchedule()
         L.check(L.lib().amf_schedule_get(self._h, C.byref(sc)))
         return dict(stencil_nodes=sc.stencil_nodes, xcd_remap=sc.xcd_remap,
-                    max_stencil_nodes=sc.max_stencil_nodes)
+                    max_stencil_nodes=sc.max_stencil_nodes, resident=sc.resident,
+                    resident_available=sc.resident_available)
 
-    def set_schedule(self, stencil_nodes: int | None = None, xcd_remap: int | None = None):
+    def set_schedule(self, stencil_nodes: int | None = None, xcd_remap: int | None = None,
+                     resident: int | None = None):
         cur = self.schedule()
         sc = L.AmfSchedule()
         sc.struct_size = C.sizeof(L.AmfSchedule)
         sc.stencil_nodes = cur["stencil_nodes"] if stencil_nodes is None else int(stencil_nodes)
         sc.xcd_remap = cur["xcd_remap"] if xcd_remap is None else int(xcd_remap)
+        sc.resident = cur["resident"] if resident is None else int(resident)
         L.check(L.lib().amf_schedule_set(self._h, C.byref(sc)))
 
     def profile_begin(self):

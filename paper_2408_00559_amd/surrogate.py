@@ -35,7 +35,7 @@ def _mlp_lib():
         lib.amf_mlp_bind.argtypes = [vp, vp, C.c_uint64, vp]
         lib.amf_mlp_set_normalization.restype = st
         fp = C.POINTER(C.c_float)
-        lib.amf_mlp_set_normalization.argtypes = [vp, fp, fp, fp, fp, vp]
+        lib.amf_mlp_set_normalization.argtypes = [vp, fp, fp, fp, fp, C.c_int32, vp]
         lib.amf_mlp_params.restype = st
         lib.amf_mlp_params.argtypes = [vp, vp, C.c_int32, vp]
         lib.amf_mlp_grads.restype = st
@@ -92,11 +92,12 @@ class Mlp:
         return ([i.layer_rows[l] for l in range(n)], [i.layer_cols[l] for l in range(n)],
                 [i.layer_w_offset[l] for l in range(n)], [i.layer_b_offset[l] for l in range(n)])
 
-    def set_normalization(self, in_mean, in_std, out_mean, out_std):
+    def set_normalization(self, in_mean, in_std, out_mean, out_std, out_log: bool = False):
         f = lambda a: (C.c_float * len(a))(*[float(v) for v in a])
-        self.norm = (np.asarray(in_mean, np.float32), np.asarray(in_std, np.float32), float(out_mean), float(out_std))
+        self.norm = (np.asarray(in_mean, np.float32), np.asarray(in_std, np.float32), float(out_mean),
+                     float(out_std), bool(out_log))
         _check(_mlp_lib().amf_mlp_set_normalization(self._h, f(in_mean), f(in_std), f([out_mean]), f([out_std]),
-                                                    _stream()))
+                                                    1 if out_log else 0, _stream()))
 
     def params(self) -> torch.Tensor:
         out = torch.empty(int(self.info.n_params), dtype=torch.float32, device=self.device)
@@ -183,7 +184,10 @@ class Surrogate:
               device: str = "cuda:0", log=None) -> "Surrogate":
         mlp = Mlp(n_in=x.shape[1], width=width, depth=depth, max_batch=max(batch, 8192), seed=seed,
                   device=device)
-        mlp.set_normalization(x.mean(axis=0), x.std(axis=0) + 1e-12, float(y.mean()), float(y.std()))
+        out_log = bool(np.all(y > 0))          # model log-prices: the residual is a relative error
+        yt_ = np.log(y) if out_log else y
+        mlp.set_normalization(x.mean(axis=0), x.std(axis=0) + 1e-12, float(yt_.mean()), float(yt_.std()),
+                              out_log)
         xt = torch.tensor(x, dtype=torch.float32, device=device)
         yt = torch.tensor(y, dtype=torch.float32, device=device)
         n = x.shape[0]

@@ -268,3 +268,40 @@ def test_batched_instances(precision, tol):
     refs = parallel(lambda p: oracle.price(p, grid, steps, nthreads=1), probs)
     for got, ref in zip(prices, refs):
         assert abs(got - ref) / abs(ref) < tol, (got, ref)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("name", ["fg2d", "d2_standard_ct", "d3_ct", "d4_ct", "d5_ct", "d6_ct",
+                                  "long_rate_axis"])
+def test_resident_schedule(name, precision, tol):
+    """a9: the unit-resident schedule (whole time loop in LDS, one workgroup per grid) against the
+    oracle, element by element after two steps, for every d and for long axis-1 lines."""
+    probs, grid = CASES[name]
+    steps = 5
+    plan = Plan(probs, grid, steps=steps, precision=precision, device=DEV)
+    sc = plan.schedule()
+    if not sc["resident_available"]:
+        pytest.skip("grids exceed the resident size limit")
+    plan.set_schedule(resident=1)
+    plan.init()
+    plan.time_step(2)
+    Y = plan.state().cpu().numpy().astype(np.float64)
+    items = unit_slices(plan)
+
+    def ref(item):
+        u, sl = item
+        p = probs[u["problem"]]
+        lv = u["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / steps, 2)
+        return oracle.inner_view(Yf, lv)
+
+    for (u, sl), r in zip(items, parallel(ref, items)):
+        assert rel_maxerr(Y[sl], r) < tol, (u, rel_maxerr(Y[sl], r))
+    # a whole solve equals the streaming schedule's
+    plan.set_schedule(resident=0)
+    p_stream = plan.price().cpu().numpy()
+    plan.set_schedule(resident=1)
+    plan.use_graph(True)
+    p_res = plan.price().cpu().numpy()
+    assert np.allclose(p_res, p_stream, rtol=1e-12 if precision == "fp64" else 1e-5)
