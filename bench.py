@@ -34,10 +34,11 @@ COPY_BYTES = 2 << 30
 def kernel_class_of(name: str):
     """Map a rocprofv3 kernel name to the library's kernel class (None for other kernels)."""
     from paper_2408_00559_amd import _lib as L
-    if "k_sweep_strided<" in name:
-        up = ", 1," in name
-        lg = "true>" in name
-        return ("sweep_update" if up else "sweep_strided") + ("_long" if lg else "")
+    for sym, lg in (("k_sweep_strided_long<", True), ("k_sweep_strided<", False)):
+        if sym in name:
+            args = [a.strip() for a in name.split(sym, 1)[1].split(">", 1)[0].split(",")]
+            up = args[-1] in ("1", "EPI_UPDATE", "amf::EPI_UPDATE")
+            return ("sweep_update" if up else "sweep_strided") + ("_long" if lg else "")
     if "k_sweep_contig<" in name:
         return "sweep_contig_long" if "true>" in name else "sweep_contig"
     if "k_stencil<" in name:

@@ -468,7 +468,10 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 while (k1 < P->n_units && P->units[ord[k1]].lv[ax] == lm) ++k1;
                 int k = k0;
                 // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each
-                const int per = (ax == 0 && lm > CONTIG_REG_LM) ? LINE_BLOCK / ((1 << lm) / SEG) : LINE_BLOCK;
+                // longer strided lines: M/SSEG threads each in blocks of SEG_BLOCK threads
+                int per = LINE_BLOCK;
+                if (ax == 0 && lm > CONTIG_REG_LM) per = LINE_BLOCK / ((1 << lm) / SEG);
+                else if (ax > 0 && lm > SHORT_LM) per = lm <= SEG_MAX_LM ? (SEG_BLOCK * SSEG) >> lm : SEG_BLOCK;
                 for (int64_t s = lo[k0]; s < lo[k1]; s += per) {
                     while (s >= lo[k + 1]) ++k;
                     SweepBlk B{};

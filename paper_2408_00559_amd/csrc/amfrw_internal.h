@@ -11,9 +11,14 @@ constexpr int NODE_BLOCK = 256;    // threads per block of the per-node kernels
 constexpr int LINE_BLOCK = 256;    // threads per block of the sweep kernels
 constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
-// Longest strided line kept whole in VGPRs by one thread (log2); longer lines stream through
-// memory in chunks of CHUNK rows.
+// Longest strided line kept whole in VGPRs by one thread (log2) in the short-line launch.
 constexpr int REG_LM = 5;
+// Longer strided lines: SSEG consecutive rows per thread, M/SSEG threads per line, blocks of
+// SEG_BLOCK threads (SEG_BLOCK*SSEG/M lines each), up to 2^SEG_MAX_LM rows; beyond that one thread
+// per line streams through memory in chunks of CHUNK rows.
+constexpr int SSEG = 16;
+constexpr int SEG_BLOCK = 1024;
+constexpr int SEG_MAX_LM = 14;
 constexpr int CHUNK = 16;
 constexpr int NXCD = 8;
 // Default nodes per thread of the time-loop operator, by precision (limited by each unit's M_0);

@@ -482,7 +482,8 @@ __device__ __forceinline__ void sweep_strided_mem(const DevPlan& P, const SweepA
     }
 }
 
-template <typename T, int EPI, bool LONG>
+// Short strided lines (up to 2^SHORT_LM rows): one thread per line.
+template <typename T, int EPI>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
     const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
@@ -493,20 +494,133 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepAr
     while (gl >= lo[k + 1]) ++k;
     const UnitDev U = P.units[P.ax_units[axis][k]];
     const Strided L = strided_geom(P, U, axis, gl - lo[k], B.lm, A.run);
-    if constexpr (!LONG) {
-        switch (B.lm) {
-        case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
-        case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
-        case 2: sweep_strided_reg<T, 2, EPI>(P, A, L); break;
-        case 3: sweep_strided_reg<T, 3, EPI>(P, A, L); break;
-        case 4: sweep_strided_reg<T, 4, EPI>(P, A, L); break;
-        default: break;   // long classes go to the LONG launch
-        }
-    } else {
-        static_assert(REG_LM == 5, "long-line dispatch assumes register lines up to 2^5");
-        if (B.lm == 5) sweep_strided_reg<T, 5, EPI>(P, A, L);
-        else sweep_strided_mem<T, EPI>(P, A, L, B.lm);
+    switch (B.lm) {
+    case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
+    case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
+    case 2: sweep_strided_reg<T, 2, EPI>(P, A, L); break;
+    case 3: sweep_strided_reg<T, 3, EPI>(P, A, L); break;
+    case 4: sweep_strided_reg<T, 4, EPI>(P, A, L); break;
+    default: break;   // longer classes go to k_sweep_strided_long
     }
+}
+
+// Inclusive scan, in segment order (reversed when `rev`), of the affine maps c -> b + a c of the
+// segments of each line; returns the map of all segments before this one applied to 0, i.e. the
+// carry entering this segment.  sa/sb: SEG_BLOCK entries of LDS, indexed segment-major.
+template <typename T>
+__device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line, int lines, bool rev,
+                                           T* sa, T* sb)
+{
+    const int s = rev ? nseg - 1 - seg : seg;
+    const int at = s * lines + line;
+    for (int off = 1; off < nseg; off <<= 1) {
+        sa[at] = a;
+        sb[at] = b;
+        __syncthreads();
+        if (s >= off) {
+            const T pa = sa[at - off * lines], pb = sb[at - off * lines];
+            b = b + a * pb;        // earlier segments first: b + a (pb + pa c)
+            a = a * pa;
+        }
+        __syncthreads();
+    }
+    sb[at] = b;
+    __syncthreads();
+    const T cin = s > 0 ? sb[at - lines] : T(0);
+    __syncthreads();
+    return cin;
+}
+
+// Long strided line split into nseg = M/SSEG segments of SSEG consecutive rows, one per thread,
+// kept in VGPRs.  Both Thomas recurrences are first order and linear, y_r = g_r inv_r - ainv_r
+// y_{r-1} and x_r = y_r - cp_r x_{r+1}: each thread runs them over its rows from a zero carry, the
+// segments' affine end maps are scanned in LDS to give every segment its true carry, and the rows
+// are corrected by the carry times the running product of the multipliers.  Every element is read
+// and written once, by the same thread (in-place safe).  All threads of the block must call it
+// (barriers); `live` is false for threads without a line.
+template <typename T, int EPI>
+__device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepArgs& A, const Strided& L, int lm,
+                                                  bool live, int seg, int nseg, int line, int lines, T* sa, T* sb)
+{
+    const int M = 1 << lm;
+    const int r0 = seg * SSEG;
+    const T* f = (const T*)P.fac + (live ? L.fac : 0);
+    T v[SSEG];
+    T y = T(0), mu = T(1);
+    if (live) {
+        const T* in = (const T*)A.in;
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) v[k] = in[L.base + (int64_t)(r0 + k) * L.stride];
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            const T ai = f[M + r0 + k];
+            y = v[k] * f[r0 + k] - ai * y;
+            mu = -ai * mu;
+            v[k] = y;
+        }
+    }
+    const T yin = segment_carry<T>(mu, y, seg, nseg, line, lines, false, sa, sb);
+    T x = T(0), nu = T(1);
+    if (live) {
+        T m = T(1);
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            m = -f[M + r0 + k] * m;
+            v[k] = v[k] + m * yin;
+        }
+#pragma unroll
+        for (int k = SSEG - 1; k >= 0; --k) {
+            const T cp = f[2 * M + r0 + k];
+            x = v[k] - cp * x;
+            nu = -cp * nu;
+            v[k] = x;
+        }
+    }
+    const T xin = segment_carry<T>(nu, x, seg, nseg, line, lines, true, sa, sb);
+    if (live) {
+        T n = T(1);
+#pragma unroll
+        for (int k = SSEG - 1; k >= 0; --k) {
+            n = -f[2 * M + r0 + k] * n;
+            v[k] = v[k] + n * xin;
+        }
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) sweep_store<T, EPI>(A, L.base + (int64_t)(r0 + k) * L.stride, v[k]);
+    }
+}
+
+// Strided lines longer than 2^SHORT_LM rows.  Classes up to 2^SEG_MAX_LM rows: SEG_BLOCK*SSEG/M
+// lines per block, thread t on line t mod lines and segment t / lines (lanes on consecutive lines,
+// coalesced); longer lines: one thread per line through memory.
+template <typename T, int EPI>
+__global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, SweepArgs A, int axis, int64_t blk0)
+{
+    __shared__ T sa[SEG_BLOCK], sb[SEG_BLOCK];
+    const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
+    const int lm = B.lm;
+    const int64_t* lo = P.ax_line_off[axis];
+    if (lm > SEG_MAX_LM) {                      // block-uniform branch
+        const int64_t gl = B.line_start + threadIdx.x;
+        if (gl >= B.line_end) return;
+        int k = B.k_start;
+        while (gl >= lo[k + 1]) ++k;
+        const UnitDev U = P.units[P.ax_units[axis][k]];
+        sweep_strided_mem<T, EPI>(P, A, strided_geom(P, U, axis, gl - lo[k], lm, A.run), lm);
+        return;
+    }
+    const int lines = (SEG_BLOCK * SSEG) >> lm;
+    const int line = threadIdx.x & (lines - 1);
+    const int seg = threadIdx.x >> (__ffs(lines) - 1);
+    const int64_t gl = B.line_start + line;
+    const bool live = gl < B.line_end;
+    Strided L{};
+    if (live) {
+        int k = B.k_start;
+        while (gl >= lo[k + 1]) ++k;
+        const UnitDev U = P.units[P.ax_units[axis][k]];
+        L = strided_geom(P, U, axis, gl - lo[k], lm, A.run);
+    }
+    sweep_strided_seg<T, EPI>(P, A, L, lm, live, seg, (1 << lm) / SSEG, line, lines, sa, sb);
 }
 
 // Axis 0 (contiguous lines).  Coefficients are formed on the fly: delta_r = tdiff_0[r] * V^2.
@@ -1063,10 +1177,12 @@ template <typename T, bool LONG>
 static void sweep_part(const DevPlan& P, int axis, int epi, const SweepArgs& a, int64_t b0, int64_t nb,
                        hipStream_t s)
 {
-    dim3 g((unsigned)nb), b(LINE_BLOCK);
+    dim3 g((unsigned)nb), b(LINE_BLOCK), bl(SEG_BLOCK);
     if (axis == 0) hipLaunchKernelGGL((k_sweep_contig<T, LONG>), g, b, 0, s, P, a, b0);
-    else if (epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE, LONG>), g, b, 0, s, P, a, axis, b0);
-    else hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE, LONG>), g, b, 0, s, P, a, axis, b0);
+    else if (!LONG && epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE>), g, b, 0, s, P, a, axis, b0);
+    else if (!LONG) hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE>), g, b, 0, s, P, a, axis, b0);
+    else if (epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_STORE>), g, bl, 0, s, P, a, axis, b0);
+    else hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_UPDATE>), g, bl, 0, s, P, a, axis, b0);
 }
 
 hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part, const SweepArgs& a,

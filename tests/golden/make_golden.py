@@ -18,6 +18,17 @@ from paper_2408_00559_amd import inputs as I  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
+def _dump(obj, name):
+    """One key per line, lists on one line (values are written with repr precision)."""
+    lines = ["{"]
+    items = list(obj.items())
+    for i, (k, v) in enumerate(items):
+        lines.append(" %s: %s%s" % (json.dumps(k), json.dumps(v), "," if i + 1 < len(items) else ""))
+    lines.append("}")
+    with open(os.path.join(HERE, name), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def run_ct4(threads):
     w = I.workload_ct4()
     p = w["problems"][0]
@@ -28,7 +39,7 @@ def run_ct4(threads):
                unit_levels=lv.tolist(), unit_coef=cf.tolist(), unit_values=list(map(float, units)),
                oracle_seconds=time.time() - t, threads=threads,
                note="FP64 CPU oracle, all component grids, written by tests/golden/make_golden.py")
-    json.dump(out, open(os.path.join(HERE, "ct4_n7_psi3_fp64.json"), "w"), indent=1)
+    _dump(out, "ct4_n7_psi3_fp64.json")
 
 
 def run_batch4(threads, count=16):
@@ -40,10 +51,18 @@ def run_batch4(threads, count=16):
     out = dict(workload=w["name"], steps=w["steps"], count=count, prices=prices,
                oracle_seconds=time.time() - t, threads=threads,
                note="FP64 CPU oracle, first %d seeded instances, written by tests/golden/make_golden.py" % count)
-    json.dump(out, open(os.path.join(HERE, "batch4_first16_fp64.json"), "w"), indent=1)
+    _dump(out, "batch4_first16_fp64.json")
+
+
+def reformat(name):
+    """Rewrite an existing file in the layout above (values unchanged)."""
+    _dump(json.load(open(os.path.join(HERE, name))), name)
 
 
 if __name__ == "__main__":
     which = sys.argv[1]
+    if which == "reformat":
+        reformat(sys.argv[2])
+        sys.exit(0)
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
     {"ct4": run_ct4, "batch4": run_batch4}[which](threads)

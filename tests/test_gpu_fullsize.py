@@ -1,0 +1,119 @@
+"""GPU parity at the benchmark sizes, in the launch configurations the benchmark may time.
+
+* d = 4, n = 7, psi = 3, 100 AMFR-W2 steps (295 component grids of 2^16..2^19 inner nodes): the
+  combined price and every component grid's interpolated value against the FP64 oracle's values
+  stored in tests/golden/ct4_n7_psi3_fp64.json (written by tests/golden/make_golden.py), for every
+  admissible launch schedule, eager and graph-replayed; one full time step element by element on
+  sampled component grids (the most elongated ones in each axis).
+* 512 seeded d = 4 instances (n = 6, psi = 1): the first 16 prices against the oracle's stored
+  values, FP64 and FP32, in the serving configuration (autotuned schedule, graph replay).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_00559_amd import autotune
+from paper_2408_00559_amd import inputs as I
+from paper_2408_00559_amd.solver import Plan
+
+from _util import parallel, rel_maxerr, unit_slices
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+HERE = os.path.dirname(os.path.abspath(__file__))
+CT4 = os.path.join(HERE, "golden", "ct4_n7_psi3_fp64.json")
+BATCH4 = os.path.join(HERE, "golden", "batch4_first16_fp64.json")
+
+
+def _golden(path):
+    if not os.path.exists(path):
+        pytest.skip("stored oracle values not present: %s" % os.path.basename(path))
+    return json.load(open(path))
+
+
+@pytest.fixture(scope="module")
+def ct4():
+    w = I.workload_ct4()
+    return w, _golden(CT4)
+
+
+def _check_units(plan, g, tol):
+    vals = plan.unit_values().cpu().numpy().astype(np.float64)
+    units = plan.units()
+    assert len(units) == len(g["unit_levels"])
+    scale = abs(g["price"])
+    for u, v in zip(units, vals):
+        k = g["unit_levels"].index(list(u["levels"]))
+        assert abs(v - g["unit_values"][k]) / scale < tol, (u["levels"], v, g["unit_values"][k])
+
+
+def test_ct4_full_size_fp64_every_schedule(ct4):
+    w, g = ct4
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp64", device=DEV)
+    cands = autotune.candidates(plan)
+    assert cands
+    for sc in cands:
+        plan.set_schedule(**sc)
+        price = float(plan.price().cpu().numpy()[0])
+        assert abs(price - g["price"]) / abs(g["price"]) < 1e-10, (sc, price, g["price"])
+        _check_units(plan, g, 1e-10)
+    # graph replay of the tuned schedule (the benchmark's configuration)
+    autotune.tune(plan, steps=1, reps=1, use_cache=False)
+    plan.use_graph(True)
+    for _ in range(2):
+        price = float(plan.price().cpu().numpy()[0])
+        assert abs(price - g["price"]) / abs(g["price"]) < 1e-10
+    _check_units(plan, g, 1e-10)
+
+
+def test_ct4_full_size_fp32(ct4):
+    w, g = ct4
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp32", device=DEV)
+    autotune.tune(plan, steps=1, reps=1, use_cache=False)
+    plan.use_graph(True)
+    price = float(plan.price().cpu().numpy()[0])
+    assert abs(price - g["price"]) / abs(g["price"]) < 1e-5, (price, g["price"])
+    _check_units(plan, g, 1e-5)
+
+
+def test_ct4_full_size_one_step_sampled_grids():
+    """One time step of the full workload; the component grids with the longest axis 0, axis 1,
+    axis 2 and axis 3 (V) compared element by element with the oracle's step."""
+    w = I.workload_ct4()
+    p = w["problems"][0]
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp64", device=DEV)
+    plan.init()
+    plan.time_step(1)
+    Y = plan.state().cpu().numpy()
+    items = unit_slices(plan)
+    picks = []
+    for ax in range(p.d):
+        best = max(items, key=lambda it: (it[0]["levels"][ax], -sum(it[0]["levels"])))
+        if best not in picks:
+            picks.append(best)
+
+    def ref(item):
+        lv = item[0]["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / w["steps"], 1)
+        return oracle.inner_view(Yf, lv)
+
+    for (u, sl), r in zip(picks, parallel(ref, picks)):
+        assert rel_maxerr(Y[sl], r) < 1e-12, (u["levels"], rel_maxerr(Y[sl], r))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_batch4_serving_configuration(precision, tol):
+    g = _golden(BATCH4)
+    w = I.workload_batch4()
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision=precision, device=DEV)
+    autotune.tune(plan, steps=1, reps=1, use_cache=False)
+    plan.use_graph(True)
+    prices = plan.price().cpu().numpy().astype(np.float64)
+    ref = np.asarray(g["prices"])
+    err = np.abs(prices[:len(ref)] - ref) / np.abs(ref)
+    assert err.max() < tol, (err.max(), plan.schedule())
+    assert np.all(np.isfinite(prices))
