@@ -41,9 +41,10 @@ def kernel_class_of(name: str):
             return ("sweep_update" if up else "sweep_strided") + ("_long" if lg else "")
     if "k_sweep_contig<" in name:
         return "sweep_contig_long" if "true>" in name else "sweep_contig"
-    if "k_stencil<" in name:
-        op = name.split("k_stencil<", 1)[1].split(">", 1)[0].split(",")[-1].strip()
-        return {"0": "operator", "1": "operator", "2": "stage1", "3": "stage2", "4": "refine"}[op]
+    for sym in ("k_stencil_vec<", "k_stencil<"):
+        if sym in name:       # template arguments <T, D, OP[, R]>
+            op = name.split(sym, 1)[1].split(">", 1)[0].split(",")[2].strip()
+            return {"0": "operator", "1": "operator", "2": "stage1", "3": "stage2", "4": "refine"}[op]
     for k in ("k_node", "k_unit_values", "k_combine", "k_resident"):
         if k in name:
             return {"k_node": "init", "k_unit_values": "unit_values", "k_combine": "combine",
@@ -325,8 +326,8 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the component grids are independent until the final "
-              "FP64 combination, and this build measures one GPU's share (see DESIGN.md for the "
-              "multi-GPU sharding design).", file=sys.stderr)
+              "FP64 combination, so a multi-GPU run would shard them and add one small reduction; "
+              "only the one-GPU share is measured here.", file=sys.stderr)
         sys.exit(2)
 
     import torch

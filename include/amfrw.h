@@ -190,7 +190,9 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
  * of independent per-node sums, which they leave unchanged).
  *   stencil_nodes: consecutive axis-1 nodes evaluated per thread by the time-loop operator
  *                  (1, 2 or 4; at most max_stencil_nodes = min(4, smallest M_1 of the plan)).
- *   xcd_remap:     1 = assign each XCD a contiguous share of the blocks (its own L2), 0 = off.
+ *   xcd_remap:     assign each XCD a contiguous share of the blocks, so that blocks reading the
+ *                  same halo planes share that XCD's L2: 1 = operator launches only, 2 = every
+ *                  streaming launch (operators, sweeps, per-node kernels), 0 = off.
  *   resident:      1 = unit-resident schedule: one workgroup per component grid runs all time steps
  *                  of a call with the grid's vectors in LDS (only when resident_available, i.e.
  *                  every grid has at most 2048 points in FP32 or 1024 in FP64); 0 = streaming

@@ -28,7 +28,7 @@ def signature(plan) -> str:
 def candidates(plan):
     sc = plan.schedule()
     nodes = [r for r in (1, 2, 4) if r <= sc["max_stencil_nodes"]]
-    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0) for r, x in itertools.product(nodes, (1, 0))]
+    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0) for r, x in itertools.product(nodes, (0, 1, 2))]
     if sc["resident_available"]:
         out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1))
     return out

@@ -468,10 +468,12 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 while (k1 < P->n_units && P->units[ord[k1]].lv[ax] == lm) ++k1;
                 int k = k0;
                 // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each
-                // longer strided lines: M/SSEG threads each in blocks of SEG_BLOCK threads
+                // longer strided lines: M/sseg threads each in blocks of SEG_BLOCK threads
                 int per = LINE_BLOCK;
+                const int ss = precision == AMF_FP64 ? SSEG_F64 : SSEG_F32;
                 if (ax == 0 && lm > CONTIG_REG_LM) per = LINE_BLOCK / ((1 << lm) / SEG);
-                else if (ax > 0 && lm > SHORT_LM) per = lm <= SEG_MAX_LM ? (SEG_BLOCK * SSEG) >> lm : SEG_BLOCK;
+                else if (ax > 0 && lm > SHORT_LM)
+                    per = lm <= seg_max_lm((int)P->elem) ? (SEG_BLOCK * ss) >> lm : SEG_BLOCK;
                 for (int64_t s = lo[k0]; s < lo[k1]; s += per) {
                     while (s >= lo[k + 1]) ++k;
                     SweepBlk B{};
@@ -986,7 +988,7 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     const int r = sc->stencil_nodes;
     if (r != 1 && r != 2 && r != 4) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2 or 4");
     if (r > P->min_m0) return fail(AMF_E_INVALID, "stencil_nodes exceeds the smallest axis-1 line");
-    if (sc->xcd_remap != 0 && sc->xcd_remap != 1) return fail(AMF_E_INVALID, "xcd_remap must be 0 or 1");
+    if (sc->xcd_remap < 0 || sc->xcd_remap > 2) return fail(AMF_E_INVALID, "xcd_remap must be 0, 1 or 2");
     if (sc->resident != 0 && sc->resident != 1) return fail(AMF_E_INVALID, "resident must be 0 or 1");
     if (sc->resident && !P->res_ok) return fail(AMF_E_INVALID, "a unit exceeds the unit-resident size limit");
     if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident) P->drop_graph();

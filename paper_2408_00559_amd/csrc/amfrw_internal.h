@@ -13,13 +13,17 @@ constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
 // Longest strided line kept whole in VGPRs by one thread (log2) in the short-line launch.
 constexpr int REG_LM = 5;
-// Longer strided lines: SSEG consecutive rows per thread, M/SSEG threads per line, blocks of
-// SEG_BLOCK threads (SEG_BLOCK*SSEG/M lines each), up to 2^SEG_MAX_LM rows; beyond that one thread
-// per line streams through memory in chunks of CHUNK rows.
-constexpr int SSEG = 16;
-constexpr int SEG_BLOCK = 1024;
-constexpr int SEG_MAX_LM = 14;
-constexpr int CHUNK = 16;
+// Longer strided lines: sseg(T) consecutive rows per thread (8 in FP64, 32 in FP32; measured on
+// the d = 4 workload), M/sseg threads per line, blocks of SEG_BLOCK threads (SEG_BLOCK*sseg/M
+// lines each), up to SEG_BLOCK*sseg rows; beyond that one thread per line streams through memory
+// in chunks of CHUNK rows.
+constexpr int SSEG_F64 = 8;
+constexpr int SSEG_F32 = 32;
+constexpr int SEG_BLOCK = 512;
+template <typename T> constexpr int sseg() { return sizeof(T) == 8 ? SSEG_F64 : SSEG_F32; }
+// log2 of the longest line the segmented solver takes, by element size
+constexpr int seg_max_lm(int elem) { return elem == 8 ? 12 : 14; }
+constexpr int CHUNK = 4;
 constexpr int NXCD = 8;
 // Default nodes per thread of the time-loop operator, by precision (limited by each unit's M_0);
 // a plan's schedule may override it.

@@ -28,7 +28,9 @@ __device__ __forceinline__ double payoff_at(const ProbDev& P, int nr, const doub
 }
 
 // Blocks are dealt round-robin to the XCDs; remap so that each XCD works on one contiguous eighth
-// of the block range, keeping stencil halos and neighbouring lines in that XCD's L2.
+// of the block range, keeping stencil halos (the neighbouring planes in the outer axes, read by the
+// adjacent blocks) in that XCD's L2.  Schedule value 1 remaps the operator kernels only, 2 every
+// streaming kernel (line blocks of uneven cost can then leave XCDs unevenly loaded).
 __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb, int on)
 {
     if (!on) return b;
@@ -47,7 +49,7 @@ __device__ __forceinline__ int find_unit(const UnitDev* units, int u, int64_t g)
 template <typename T, int D, int MODE>   // MODE 0: Y = g;  1: Y = 0;  2: Y = W + g
 __global__ __launch_bounds__(NODE_BLOCK) void k_node(DevPlan P, const T* Win, T* Y)
 {
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd);
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd == 2);
     const int64_t g = lb * NODE_BLOCK + threadIdx.x;
     if (g >= P.total) return;
     const int u = find_unit(P.units, P.blk_unit[lb], g);
@@ -90,7 +92,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_node(DevPlan P, const T* Win, T*
 template <typename T, int D, int OP>
 __global__ __launch_bounds__(NODE_BLOCK) void k_stencil(DevPlan P, StencilArgs A)
 {
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd);
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd != 0);
     const int64_t g = lb * NODE_BLOCK + threadIdx.x;
     if (g >= P.total) return;
     const int u = find_unit(P.units, P.blk_unit[lb], g);
@@ -217,7 +219,7 @@ template <typename T, int D, int OP, int R>
 __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilArgs A)
 {
     static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
-    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd);
+    const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd != 0);
     const int64_t g = (lb * NODE_BLOCK + threadIdx.x) * R;
     if (g >= P.total) return;
     const int u = find_unit(P.units, P.blk_unit_r[R == 4 ? 2 : 1][lb], g);
@@ -244,31 +246,40 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
     const T* X1 = (const T*)A.X1;
     const T av = (T)A.a;
     const bool has_left = j[0] > 1, has_right = j[0] + R - 1 < M[0];
-    // a row of R nodes at offset o (plus the axis-0 end values when `ends`), zero on faces
-    auto load_row = [&](int64_t o, bool ends, T* v) {
-        load_vec<T, R>(X0 + g + o, v + 1);
-        if constexpr (OP == OP_STAGE2) {
-            T w[R];
-            load_vec<T, R>(X1 + g + o, w);
+    const int lane = threadIdx.x & 63;
+    auto X = [&](int64_t idx) -> T {
+        if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
+        else return X0[idx];
+    };
+    // v[1..R]: the row of R nodes at offset o (0 where !ok).  With `ends` (wave-uniform: every
+    // active lane must reach the shuffles) also v[0], v[R+1]: the axis-0 neighbours, taken from
+    // the adjacent lanes' rows (lanes hold consecutive R-node chunks), loaded only by the lanes
+    // at the wave's edges, 0 on the lower face and beyond the line's end.
+    auto load_row = [&](int64_t o, bool ends, bool ok, T* v) {
+        if (ok) {
+            load_vec<T, R>(X0 + g + o, v + 1);
+            if constexpr (OP == OP_STAGE2) {
+                T w[R];
+                load_vec<T, R>(X1 + g + o, w);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
+                for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[1 + r] = T(0);
         }
         v[0] = T(0);
         v[R + 1] = T(0);
         if (ends) {
-            if (has_left) {
-                v[0] = X0[g + o - 1];
-                if constexpr (OP == OP_STAGE2) v[0] += av * X1[g + o - 1];
-            }
-            if (has_right) {
-                v[R + 1] = X0[g + o + R];
-                if constexpr (OP == OP_STAGE2) v[R + 1] += av * X1[g + o + R];
-            }
+            const T lv = __shfl_up(v[R], 1);
+            const T rv = __shfl_down(v[1], 1);
+            if (ok && has_left) v[0] = lane == 0 ? X(g + o - 1) : lv;
+            if (ok && has_right) v[R + 1] = lane == 63 ? X(g + o + R) : rv;
         }
     };
 
     T c[R + 2];
-    load_row(0, true, c);
+    load_row(0, true, true, c);
     T acc[R];
     // axis 0: second differences with the Neumann ghost at j_0 = M_0; coefficients per node
     const T* t0 = tab + U.tab[0];
@@ -290,15 +301,9 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
     for (int k = 1; k < D; ++k) {
         T rm[R + 2], rp[R + 2];
         const bool up_ok = j[k] != M[k];
-        if (j[k] > 1) {
-            load_row(-E[k], up_ok, rm);
-        } else {
-#pragma unroll
-            for (int r = 0; r < R + 2; ++r) rm[r] = T(0);
-        }
-        if (up_ok) {
-            load_row(E[k], true, rp);
-        } else {
+        load_row(-E[k], true, j[k] > 1, rm);
+        load_row(E[k], true, up_ok, rp);
+        if (!up_ok) {
 #pragma unroll
             for (int r = 0; r < R + 2; ++r) rp[r] = rm[r];
         }
@@ -339,13 +344,10 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
         for (int k = i + 1; k < D; ++k) {
             if (j[i] != M[i] && j[k] != M[k]) {
                 T pp[R + 2], mm[R + 2], pm[R + 2], mp[R + 2];
-                load_row(E[i] + E[k], false, pp);
-                if (j[i] > 1 && j[k] > 1) load_row(-E[i] - E[k], false, mm);
-                else for (int r = 0; r < R + 2; ++r) mm[r] = T(0);
-                if (j[k] > 1) load_row(E[i] - E[k], false, pm);
-                else for (int r = 0; r < R + 2; ++r) pm[r] = T(0);
-                if (j[i] > 1) load_row(-E[i] + E[k], false, mp);
-                else for (int r = 0; r < R + 2; ++r) mp[r] = T(0);
+                load_row(E[i] + E[k], false, true, pp);
+                load_row(-E[i] - E[k], false, j[i] > 1 && j[k] > 1, mm);
+                load_row(E[i] - E[k], false, j[k] > 1, pm);
+                load_row(-E[i] + E[k], false, j[i] > 1, mp);
                 const T cik = ((k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i]) * tmix[i] * tmix[k];
 #pragma unroll
                 for (int r = 0; r < R; ++r) acc[r] += cik * (pp[r + 1] + mm[r + 1] - pm[r + 1] - mp[r + 1]);
@@ -486,7 +488,7 @@ __device__ __forceinline__ void sweep_strided_mem(const DevPlan& P, const SweepA
 template <typename T, int EPI>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
-    const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
+    const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
     const int64_t gl = B.line_start + threadIdx.x;
     if (gl >= B.line_end) return;
     const int64_t* lo = P.ax_line_off[axis];
@@ -506,32 +508,34 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepAr
 
 // Inclusive scan, in segment order (reversed when `rev`), of the affine maps c -> b + a c of the
 // segments of each line; returns the map of all segments before this one applied to 0, i.e. the
-// carry entering this segment.  sa/sb: SEG_BLOCK entries of LDS, indexed segment-major.
+// carry entering this segment.  sh: 4*SEG_BLOCK entries of LDS (two ping-pong buffers of (a, b),
+// segment-major), so each doubling round needs one barrier.
 template <typename T>
-__device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line, int lines, bool rev,
-                                           T* sa, T* sb)
+__device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line, int lines, bool rev, T* sh)
 {
     const int s = rev ? nseg - 1 - seg : seg;
     const int at = s * lines + line;
+    T* buf = sh;
+    buf[at] = a;
+    buf[SEG_BLOCK + at] = b;
+    __syncthreads();
     for (int off = 1; off < nseg; off <<= 1) {
-        sa[at] = a;
-        sb[at] = b;
-        __syncthreads();
         if (s >= off) {
-            const T pa = sa[at - off * lines], pb = sb[at - off * lines];
+            const T pa = buf[at - off * lines], pb = buf[SEG_BLOCK + at - off * lines];
             b = b + a * pb;        // earlier segments first: b + a (pb + pa c)
             a = a * pa;
         }
+        buf = (buf == sh) ? sh + 2 * SEG_BLOCK : sh;
+        buf[at] = a;
+        buf[SEG_BLOCK + at] = b;
         __syncthreads();
     }
-    sb[at] = b;
-    __syncthreads();
-    const T cin = s > 0 ? sb[at - lines] : T(0);
-    __syncthreads();
+    const T cin = s > 0 ? buf[SEG_BLOCK + at - lines] : T(0);
+    __syncthreads();           // the buffers are reused by the next scan
     return cin;
 }
 
-// Long strided line split into nseg = M/SSEG segments of SSEG consecutive rows, one per thread,
+// Long strided line split into nseg = M/S segments of S = sseg<T>() consecutive rows, one per thread,
 // kept in VGPRs.  Both Thomas recurrences are first order and linear, y_r = g_r inv_r - ainv_r
 // y_{r-1} and x_r = y_r - cp_r x_{r+1}: each thread runs them over its rows from a zero carry, the
 // segments' affine end maps are scanned in LDS to give every segment its true carry, and the rows
@@ -540,9 +544,10 @@ __device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line
 // (barriers); `live` is false for threads without a line.
 template <typename T, int EPI>
 __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepArgs& A, const Strided& L, int lm,
-                                                  bool live, int seg, int nseg, int line, int lines, T* sa, T* sb)
+                                                  bool live, int seg, int nseg, int line, int lines, T* sh)
 {
     const int M = 1 << lm;
+    constexpr int SSEG = sseg<T>();
     const int r0 = seg * SSEG;
     const T* f = (const T*)P.fac + (live ? L.fac : 0);
     T v[SSEG];
@@ -559,7 +564,7 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
             v[k] = y;
         }
     }
-    const T yin = segment_carry<T>(mu, y, seg, nseg, line, lines, false, sa, sb);
+    const T yin = segment_carry<T>(mu, y, seg, nseg, line, lines, false, sh);
     T x = T(0), nu = T(1);
     if (live) {
         T m = T(1);
@@ -576,7 +581,7 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
             v[k] = x;
         }
     }
-    const T xin = segment_carry<T>(nu, x, seg, nseg, line, lines, true, sa, sb);
+    const T xin = segment_carry<T>(nu, x, seg, nseg, line, lines, true, sh);
     if (live) {
         T n = T(1);
 #pragma unroll
@@ -589,22 +594,23 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
     }
 }
 
-// Strided lines longer than 2^SHORT_LM rows.  Classes up to 2^SEG_MAX_LM rows: SEG_BLOCK*SSEG/M
+// Strided lines longer than 2^SHORT_LM rows.  Classes up to SEG_BLOCK*sseg rows: SEG_BLOCK*sseg/M
 // lines per block, thread t on line t mod lines and segment t / lines (lanes on consecutive lines,
 // coalesced); longer lines: one thread per line through memory.
 template <typename T, int EPI>
 __global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
-    __shared__ T sa[SEG_BLOCK], sb[SEG_BLOCK];
-    const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
+    __shared__ T sh[4 * SEG_BLOCK];
+    const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
     const int lm = B.lm;
     const int64_t* lo = P.ax_line_off[axis];
-    if (lm > SEG_MAX_LM) {                      // block-uniform branch
+    constexpr int SSEG = sseg<T>();
+    if (lm > seg_max_lm((int)sizeof(T))) {      // block-uniform branch
         const int64_t gl = B.line_start + threadIdx.x;
         if (gl >= B.line_end) return;
         int k = B.k_start;
         while (gl >= lo[k + 1]) ++k;
-        const UnitDev U = P.units[P.ax_units[axis][k]];
+        const UnitDev& U = P.units[P.ax_units[axis][k]];
         sweep_strided_mem<T, EPI>(P, A, strided_geom(P, U, axis, gl - lo[k], lm, A.run), lm);
         return;
     }
@@ -617,10 +623,10 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, Swe
     if (live) {
         int k = B.k_start;
         while (gl >= lo[k + 1]) ++k;
-        const UnitDev U = P.units[P.ax_units[axis][k]];
+        const UnitDev& U = P.units[P.ax_units[axis][k]];
         L = strided_geom(P, U, axis, gl - lo[k], lm, A.run);
     }
-    sweep_strided_seg<T, EPI>(P, A, L, lm, live, seg, (1 << lm) / SSEG, line, lines, sa, sb);
+    sweep_strided_seg<T, EPI>(P, A, L, lm, live, seg, (1 << lm) / SSEG, line, lines, sh);
 }
 
 // Axis 0 (contiguous lines).  Coefficients are formed on the fly: delta_r = tdiff_0[r] * V^2.
@@ -767,7 +773,7 @@ __device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Cont
 template <typename T, bool LONG>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArgs A, int64_t blk0)
 {
-    const SweepBlk B = P.ax_blk[0][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd)];
+    const SweepBlk B = P.ax_blk[0][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
     const int lm = B.lm;
     const int sp = lm > CONTIG_REG_LM ? (1 << lm) / SEG : 1;   // lanes per line
     const int64_t gl = B.line_start + threadIdx.x / sp;
