@@ -415,7 +415,7 @@ amf_status amf_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_
     N->bpad_max = pad_to(max_batch, KSTEP);
     N->seed = seed;
     N->nl = depth + 1;
-    // layers: K padded to 32 at the input, N padded to 16 at the output
+    // layers: K padded to KSTEP at the input, N padded to OUT_PAD at the output
     int64_t po = 0, bo = 0;
     for (int l = 0; l < N->nl; ++l) {
         LayerDev& Ld = N->L[l];
