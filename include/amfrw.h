@@ -197,6 +197,11 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
  *                  of a call with the grid's vectors in LDS (only when resident_available, i.e.
  *                  every grid has at most 2048 points in FP32 or 1024 in FP64); 0 = streaming
  *                  schedule: one launch per operator / axis over all grids.
+ *   fuse_axis0:    streaming schedule only: 1 = the time-loop operator launches also solve the
+ *                  axis-1 systems of the first AMF factor (Lemma lema:ls) on the values they
+ *                  produce, so no separate axis-1 sweep runs; allowed when stencil_nodes >= 2 and
+ *                  256 * stencil_nodes >= the longest axis-1 line (fuse_max_axis0 reports that
+ *                  line length); 0 = separate axis-1 sweep launches.
  * amf_schedule_set may be called at any time between enqueued calls; AMF_E_INVALID otherwise. */
 typedef struct {
     uint32_t struct_size;
@@ -205,6 +210,8 @@ typedef struct {
     int32_t max_stencil_nodes;   /* read-only: filled by amf_schedule_get */
     int32_t resident;
     int32_t resident_available;  /* read-only: filled by amf_schedule_get */
+    int32_t fuse_axis0;
+    int32_t fuse_max_axis0;      /* read-only: longest axis-1 line M_1 of the plan */
 } amf_schedule;
 
 amf_status amf_schedule_get(const amf_plan* plan, amf_schedule* out);

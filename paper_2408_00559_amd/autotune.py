@@ -28,9 +28,12 @@ def signature(plan) -> str:
 def candidates(plan):
     sc = plan.schedule()
     nodes = [r for r in (1, 2, 4) if r <= sc["max_stencil_nodes"]]
-    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0) for r, x in itertools.product(nodes, (0, 1, 2))]
+    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=0)
+           for r, x in itertools.product(nodes, (0, 1, 2))]
+    out += [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=1)
+            for r, x in itertools.product(nodes, (0, 1)) if plan.fuse_allowed(r)]
     if sc["resident_available"]:
-        out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1))
+        out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1, fuse_axis0=0))
     return out
 
 

@@ -48,7 +48,8 @@ struct amf_plan {
     std::vector<ProbDev> probdev;
     std::vector<int32_t> blk_unit;
     std::vector<int32_t> blk_unit_r[3];    // node blocks of NODE_BLOCK * {1, 2, 4} nodes
-    int stencil_r = 1, min_m0 = 1, xcd = 1;
+    int stencil_r = 1, min_m0 = 1, max_m0 = 1, xcd = 1;
+    int fuse0 = 0;                         // fused axis-0 solve in the operator launches
     bool res_ok = false;                   // every unit fits the unit-resident schedule
     int resident = 0, res_lds_len = 0;
     std::vector<int32_t> ax_units[MAXD];
@@ -361,7 +362,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                     }
                 }
             P->probdev.push_back(pd);
-            // Thomas factors per (strided axis, level, V level) in use, both runs
+            // Thomas factors per (axis, level, V level) in use, both runs (axis 0: the fused solve)
             std::vector<std::vector<int64_t>> fac_of(d, std::vector<int64_t>(17 * 17, -1));
             // FP64 weights delta_r = d_ax / h_ax^2 along a line (as the coefficient tables hold them)
             auto delta_of = [&](int ax, int L, int LV, int jv, const std::vector<double>& t,
@@ -374,7 +375,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             };
             std::vector<int64_t> unit_fac((size_t)ng * d, 0);
             for (int g = 0; g < ng; ++g)
-                for (int i = 1; i < d; ++i) {
+                for (int i = 0; i < d; ++i) {
                     const int L = glv[g][i], LV = glv[g][d - 1];
                     const int key = (i < d - 1) ? L * 17 + LV : L * 17 + L;
                     if (fac_of[i][key] < 0) {
@@ -393,7 +394,10 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 }
             for (int g = 0; g < ng; ++g) {
                 UnitDev U{};
-                P->total = (P->total + UNIT_ALIGN - 1) / UNIT_ALIGN * UNIT_ALIGN;
+                // offsets are multiples of min(M_0, 1024) as well, so that node blocks of the
+                // fused operator (NODE_BLOCK * R >= M_0 nodes) never split an axis-0 line
+                const int64_t al = std::max<int64_t>(UNIT_ALIGN, std::min<int64_t>(1024, (int64_t)1 << glv[g][0]));
+                P->total = (P->total + al - 1) / al * al;
                 U.off = P->total;
                 U.prob = p;
                 int ls = 0;
@@ -433,9 +437,13 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         block_table(NODE_BLOCK, P->blk_unit);
         for (int k = 0; k < 3; ++k) block_table((int64_t)NODE_BLOCK << k, P->blk_unit_r[k]);
         // time-loop operator: R consecutive axis-0 nodes per thread, R <= every unit's M_0
-        int min_m0 = 1 << 16;
-        for (int u = 0; u < P->n_units; ++u) min_m0 = std::min(min_m0, 1 << P->units[u].lv[0]);
+        int min_m0 = 1 << 16, max_m0 = 1;
+        for (int u = 0; u < P->n_units; ++u) {
+            min_m0 = std::min(min_m0, 1 << P->units[u].lv[0]);
+            max_m0 = std::max(max_m0, 1 << P->units[u].lv[0]);
+        }
         P->min_m0 = min_m0;
+        P->max_m0 = max_m0;
         int max_lsum = 0;
         for (int u = 0; u < P->n_units; ++u) max_lsum = std::max(max_lsum, (int)P->units[u].lsum);
         P->res_ok = max_lsum <= (precision == AMF_FP64 ? RES_MAX_LSUM_F64 : RES_MAX_LSUM_F32);
@@ -665,8 +673,10 @@ hipError_t timed(amf_plan* P, int kclass, double bytes, hipStream_t s, Fn&& fn)
 hipError_t run_stencil(amf_plan* P, int op, const StencilArgs& a, hipStream_t s)
 {
     // vectors read or written once: F only 2; stage 1 (W, F(g), out) 3; stage 2 (W, K1, F(g), out)
-    // 4; refinement (K^(d), K^(0) in and out) 3
-    const double nv = (op == OP_F_PAYOFF || op == OP_F_ZERO) ? 2.0 : (op == OP_STAGE2 ? 4.0 : 3.0);
+    // 4; refinement (K^(d), K^(0) in and out) 3; the fused stage operators also write the solved
+    // values (one more vector), the fused refinement writes only those
+    double nv = (op == OP_F_PAYOFF || op == OP_F_ZERO) ? 2.0 : (op == OP_STAGE2 ? 4.0 : 3.0);
+    if (a.S != nullptr && op != OP_REFINE) nv += 1.0;
     const int kc = op == OP_STAGE1 ? AMF_K_STAGE1 : op == OP_STAGE2 ? AMF_K_STAGE2
                  : op == OP_REFINE ? AMF_K_REFINE : AMF_K_OPERATOR;
     return timed(P, kc, nv * P->vbytes(), s, [&] { return launch_stencil(P->dev, P->prec, op, a, s); });
@@ -746,12 +756,14 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
     const int sel_dt = CST_RUN + 3 * run, sel_th = sel_dt + 2;
     void *Wv = P->vec(V_W), *K1 = P->vec(V_K1), *A = P->vec(V_A), *B = P->vec(V_B), *G = P->vec(V_G);
     const double a21 = P->sch.a[1 * AMF_MAX_STAGES + 0], q21 = P->sch.q[1 * AMF_MAX_STAGES + 0];
+    const bool fuse = P->fuse0 != 0;
     hipError_t e;
-    // (I - nu dt A_1) .. (I - nu dt A_d) applied in axis order; the first solve is out of place
-    auto chain = [&](const void* in, void* dst, bool last_update) -> hipError_t {
-        for (int ax = 0; ax < d; ++ax) {
+    // (I - nu dt A_1) .. (I - nu dt A_d) applied in axis order from axis `first` (1 when the operator
+    // launch already solved axis 0); the first solve reads `in`, the others work in place on `dst`
+    auto chain = [&](const void* in, void* dst, bool last_update, int first) -> hipError_t {
+        for (int ax = first; ax < d; ++ax) {
             SweepArgs a{};
-            a.in = ax == 0 ? in : dst;
+            a.in = ax == first ? in : dst;
             a.out = dst;
             a.run = run;
             int epi = EPI_STORE;
@@ -767,39 +779,50 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
         }
         return hipSuccess;
     };
-    // ---- stage 1: K^(0) = dt F(Y) = dt (F0(W) + F(g))
+    const int first = fuse ? 1 : 0;
+    // ---- stage 1: K^(0) = dt F(Y) = dt (F0(W) + F(g)) -> A (and its axis-0 solve -> B)
     StencilArgs st{};
     st.X0 = Wv;
     st.cG = G;
     st.W = A;
+    st.S = fuse ? B : nullptr;
+    st.run = run;
     st.scale_sel = sel_dt;
     if ((e = run_stencil(P, OP_STAGE1, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    if ((e = chain(A, B, false)) != hipSuccess) return hip_fail(e, "sweep");
-    // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d))
+    if ((e = chain(fuse ? B : A, B, false, first)) != hipSuccess) return hip_fail(e, "sweep");
+    // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d)) -> A (fused: its axis-0 solve -> K1)
     st = StencilArgs{};
     st.X0 = B;
     st.W = A;
+    st.S = fuse ? K1 : nullptr;
+    st.run = run;
     st.scale_sel = sel_th;
     if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    if ((e = chain(A, K1, false)) != hipSuccess) return hip_fail(e, "sweep");
-    // ---- stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1
+    if ((e = chain(fuse ? K1 : A, K1, false, first)) != hipSuccess) return hip_fail(e, "sweep");
+    // ---- stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1 -> A (and its axis-0 solve -> B)
     st = StencilArgs{};
     st.X0 = Wv;
     st.X1 = K1;
     st.cG = G;
     st.W = A;
+    st.S = fuse ? B : nullptr;
+    st.run = run;
     st.a = a21;
     st.q = q21;
     st.scale_sel = sel_dt;
     if ((e = run_stencil(P, OP_STAGE2, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    if ((e = chain(A, B, false)) != hipSuccess) return hip_fail(e, "sweep");
+    if ((e = chain(fuse ? B : A, B, false, first)) != hipSuccess) return hip_fail(e, "sweep");
+    // fused: the refinement reads K^(0) (A) and K^(d) (B, with halo) and writes its axis-0 solve
+    // over A, which no other block reads
     st = StencilArgs{};
     st.X0 = B;
     st.W = A;
+    st.S = fuse ? A : nullptr;
+    st.run = run;
     st.scale_sel = sel_th;
     if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
     // second chain of stage 2 ends in W += b1 K1 + b2 K2
-    if ((e = chain(A, B, true)) != hipSuccess) return hip_fail(e, "sweep");
+    if ((e = chain(A, fuse ? A : B, true, first)) != hipSuccess) return hip_fail(e, "sweep");
     return AMF_OK;
 }
 
@@ -979,6 +1002,8 @@ amf_status amf_schedule_get(const amf_plan* P, amf_schedule* out)
     out->max_stencil_nodes = std::min(4, P->min_m0);
     out->resident = P->resident;
     out->resident_available = P->res_ok ? 1 : 0;
+    out->fuse_axis0 = P->fuse0;
+    out->fuse_max_axis0 = P->max_m0;
     return AMF_OK;
 }
 
@@ -991,8 +1016,13 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (sc->xcd_remap < 0 || sc->xcd_remap > 2) return fail(AMF_E_INVALID, "xcd_remap must be 0, 1 or 2");
     if (sc->resident != 0 && sc->resident != 1) return fail(AMF_E_INVALID, "resident must be 0 or 1");
     if (sc->resident && !P->res_ok) return fail(AMF_E_INVALID, "a unit exceeds the unit-resident size limit");
-    if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident) P->drop_graph();
+    if (sc->fuse_axis0 != 0 && sc->fuse_axis0 != 1) return fail(AMF_E_INVALID, "fuse_axis0 must be 0 or 1");
+    if (sc->fuse_axis0 && (r < 2 || NODE_BLOCK * r < P->max_m0))
+        return fail(AMF_E_INVALID, "fuse_axis0 needs stencil_nodes >= 2 and 256 * stencil_nodes >= the longest axis-1 line");
+    if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident || sc->fuse_axis0 != P->fuse0)
+        P->drop_graph();
     P->resident = sc->resident;
+    P->fuse0 = sc->fuse_axis0;
     P->stencil_r = r;
     P->xcd = sc->xcd_remap;
     P->dev.stencil_r = r;

@@ -116,9 +116,11 @@ struct StencilArgs {
     const void* X1;
     const void* cG;
     void* W;
+    void* S;              // non-null: fused axis-0 solve, solved values written here
     double a, q;          // OP_STAGE2 coefficients
     double scale;         // explicit scale when scale_sel < 0
     int scale_sel;        // else index into the per-problem constant block
+    int run;              // factor tables of the fused solve: 0 coarse, 1 fine (Richardson) step
 };
 
 enum SweepEpi : int { EPI_STORE = 0, EPI_UPDATE = 1 };

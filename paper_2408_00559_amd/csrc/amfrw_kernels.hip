@@ -215,167 +215,312 @@ __device__ __forceinline__ void load_vec(const T* p, T* dst)
     for (int r = 0; r < R; ++r) dst[r] = x[r];
 }
 
-template <typename T, int D, int OP, int R>
+
+template <typename T, int R>
+__device__ __forceinline__ void store_vec(T* p, const T* v)
+{
+    typedef T vt __attribute__((ext_vector_type(R)));
+    vt x;
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[r] = v[r];
+    *(vt*)p = x;
+}
+
+// Carry entering each segment of a line whose segments sit on consecutive threads of the block
+// (segment `pos` of `nseg`, counted along the scan direction: forward = increasing rows, reversed =
+// decreasing rows): inclusive scan of the affine maps c -> b + a c, one doubling round per
+// __syncthreads_or, which also makes the round count block-uniform when the block holds lines of
+// different lengths.  sh: 4*NODE_BLOCK entries of LDS (two ping-pong buffers of (a, b)).
+template <typename T>
+__device__ __forceinline__ T adjacent_carry(T a, T b, int pos, int nseg, bool rev, T* sh)
+{
+    const int tid = threadIdx.x;
+    const int dir = rev ? 1 : -1;          // where the earlier segments of the scan sit
+    T* buf = sh;
+    buf[tid] = a;
+    buf[NODE_BLOCK + tid] = b;
+    int off = 1;
+    while (__syncthreads_or(off < nseg)) {
+        if (off < nseg && pos >= off) {
+            const int at = tid + dir * off;
+            const T pa = buf[at], pb = buf[NODE_BLOCK + at];
+            b = b + a * pb;
+            a = a * pa;
+        }
+        buf = (buf == sh) ? sh + 2 * NODE_BLOCK : sh;
+        buf[tid] = a;
+        buf[NODE_BLOCK + tid] = b;
+        off <<= 1;
+    }
+    const T cin = pos > 0 ? buf[NODE_BLOCK + tid + dir] : T(0);
+    __syncthreads();
+    return cin;
+}
+
+// The same carry when every line's segments lie inside one wave (nseg <= 64; lines start at lane
+// multiples of nseg): a doubling scan over lane shuffles, as many rounds as the wave's longest line
+// needs, no LDS and no barrier.
+template <typename T>
+__device__ __forceinline__ T wave_carry(T a, T b, int pos, int nseg, bool rev)
+{
+    for (int off = 1; __any(off < nseg); off <<= 1) {
+        const T pa = rev ? __shfl_down(a, off) : __shfl_up(a, off);
+        const T pb = rev ? __shfl_down(b, off) : __shfl_up(b, off);
+        if (off < nseg && pos >= off) {
+            b = b + a * pb;
+            a = a * pa;
+        }
+    }
+    const T prev = rev ? __shfl_down(b, 1) : __shfl_up(b, 1);
+    return pos > 0 ? prev : T(0);
+}
+
+// Axis-0 solve (I - nu dt A_1) x = v of the R rows r0..r0+R-1 this thread holds (segment s of the
+// line's nseg = M0/R segments, consecutive threads), with the tabulated factors f = (inv, a inv,
+// c') of the line: both Thomas recurrences from zero carries, carries scanned across the line's
+// threads (in-wave shuffles unless a line of the block spans several waves), rows corrected.
+// Every thread of the block must call it.
+template <typename T, int R>
+__device__ __forceinline__ void axis0_segment_solve(T* v, const T* f, int M0, int s, int nseg, bool live, T* sh)
+{
+    const bool wide = __syncthreads_or(nseg > 64);
+    const int r0 = s * R;
+    T y = T(0), mu = T(1);
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const T ai = f[M0 + r0 + k];
+            y = v[k] * f[r0 + k] - ai * y;
+            mu = -ai * mu;
+            v[k] = y;
+        }
+    }
+    const T yin = wide ? adjacent_carry<T>(mu, y, s, nseg, false, sh) : wave_carry<T>(mu, y, s, nseg, false);
+    T x = T(0), nu = T(1);
+    if (live) {
+        T m = T(1);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            m = -f[M0 + r0 + k] * m;
+            v[k] = v[k] + m * yin;
+        }
+#pragma unroll
+        for (int k = R - 1; k >= 0; --k) {
+            const T cp = f[2 * M0 + r0 + k];
+            x = v[k] - cp * x;
+            nu = -cp * nu;
+            v[k] = x;
+        }
+    }
+    const T xin = wide ? adjacent_carry<T>(nu, x, nseg - 1 - s, nseg, true, sh)
+                       : wave_carry<T>(nu, x, nseg - 1 - s, nseg, true);
+    if (live) {
+        T n = T(1);
+#pragma unroll
+        for (int k = R - 1; k >= 0; --k) {
+            n = -f[2 * M0 + r0 + k] * n;
+            v[k] = v[k] + n * xin;
+        }
+    }
+}
+
+// Time-loop operator over R consecutive axis-0 nodes per thread.  FUSE: the block also solves the
+// axis-0 systems of the first AMF factor on the values it produced (its lines lie whole inside the
+// block: unit offsets are multiples of min(M0, 1024) and NODE_BLOCK*R >= M0) and writes them to
+// A.S; the stage operators still write K^(0) to A.W (the refinement reads it), the refinement
+// writes only the solved values.
+template <typename T, int D, int OP, int R, bool FUSE>
 __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilArgs A)
 {
     static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd != 0);
     const int64_t g = (lb * NODE_BLOCK + threadIdx.x) * R;
-    if (g >= P.total) return;
-    const int u = find_unit(P.units, P.blk_unit_r[R == 4 ? 2 : 1][lb], g);
-    const UnitDev U = P.units[u];
-    const int64_t loc = g - U.off;
-    if (loc >= ((int64_t)1 << U.lsum)) return;   // alignment padding
-    const ProbDev& PR = P.probs[U.prob];
-    const T* tab = (const T*)P.tab;
-    const T* cst = tab + PR.cst;
+    bool live = g < P.total;
+    if constexpr (!FUSE) {
+        if (!live) return;
+    }
+    int u = 0;
+    int64_t loc = 0;
+    if (live) {
+        u = find_unit(P.units, P.blk_unit_r[R == 4 ? 2 : 1][lb], g);
+        loc = g - P.units[u].off;
+        live = loc < ((int64_t)1 << P.units[u].lsum);     // else alignment padding
+    }
+    if constexpr (!FUSE) {
+        if (!live) return;
+    }
+    T o[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) o[r] = T(0);
+    // the operator itself is written out in the kernel body (an extracted device function costs
+    // ~50 VGPRs here: its lambdas lose track of which values are wave-uniform)
+    if (live) {
+        const UnitDev U = P.units[u];
+            const ProbDev& PR = P.probs[U.prob];
+            const T* tab = (const T*)P.tab;
+            const T* cst = tab + PR.cst;
 
-    int j[D], M[D];
-    int64_t E[D];
-    {
-        int sh = 0;
+            int j[D], M[D];
+            int64_t E[D];
+            {
+                int sh = 0;
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            M[i] = 1 << U.lv[i];
-            E[i] = (int64_t)1 << sh;
-            j[i] = (int)((loc >> sh) & (M[i] - 1)) + 1;   // j[0] = first of the R nodes
-            sh += U.lv[i];
-        }
-    }
-    const T* X0 = (const T*)A.X0;
-    const T* X1 = (const T*)A.X1;
-    const T av = (T)A.a;
-    const bool has_left = j[0] > 1, has_right = j[0] + R - 1 < M[0];
-    const int lane = threadIdx.x & 63;
-    auto X = [&](int64_t idx) -> T {
-        if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
-        else return X0[idx];
-    };
-    // v[1..R]: the row of R nodes at offset o (0 where !ok).  With `ends` (wave-uniform: every
-    // active lane must reach the shuffles) also v[0], v[R+1]: the axis-0 neighbours, taken from
-    // the adjacent lanes' rows (lanes hold consecutive R-node chunks), loaded only by the lanes
-    // at the wave's edges, 0 on the lower face and beyond the line's end.
-    auto load_row = [&](int64_t o, bool ends, bool ok, T* v) {
-        if (ok) {
-            load_vec<T, R>(X0 + g + o, v + 1);
-            if constexpr (OP == OP_STAGE2) {
-                T w[R];
-                load_vec<T, R>(X1 + g + o, w);
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
+                for (int i = 0; i < D; ++i) {
+                    M[i] = 1 << U.lv[i];
+                    E[i] = (int64_t)1 << sh;
+                    j[i] = (int)((loc >> sh) & (M[i] - 1)) + 1;   // j[0] = first of the R nodes
+                    sh += U.lv[i];
+                }
             }
-        } else {
+            const T* X0 = (const T*)A.X0;
+            const T* X1 = (const T*)A.X1;
+            const T av = (T)A.a;
+            const bool has_left = j[0] > 1, has_right = j[0] + R - 1 < M[0];
+            const int lane = threadIdx.x & 63;
+            auto X = [&](int64_t idx) -> T {
+                if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
+                else return X0[idx];
+            };
+            // v[1..R]: the row of R nodes at offset o (0 where !ok).  With `ends` (wave-uniform: every
+            // active lane must reach the shuffles) also v[0], v[R+1]: the axis-0 neighbours, taken from
+            // the adjacent lanes' rows (lanes hold consecutive R-node chunks), loaded only by the lanes
+            // at the wave's edges, 0 on the lower face and beyond the line's end.
+            auto load_row = [&](int64_t o, bool ends, bool ok, T* v) {
+                if (ok) {
+                    load_vec<T, R>(X0 + g + o, v + 1);
+                    if constexpr (OP == OP_STAGE2) {
+                        T w[R];
+                        load_vec<T, R>(X1 + g + o, w);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[1 + r] = T(0);
-        }
-        v[0] = T(0);
-        v[R + 1] = T(0);
-        if (ends) {
-            const T lv = __shfl_up(v[R], 1);
-            const T rv = __shfl_down(v[1], 1);
-            if (ok && has_left) v[0] = lane == 0 ? X(g + o - 1) : lv;
-            if (ok && has_right) v[R + 1] = lane == 63 ? X(g + o + R) : rv;
-        }
-    };
+                        for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[1 + r] = T(0);
+                }
+                v[0] = T(0);
+                v[R + 1] = T(0);
+                if (ends) {
+                    const T lv = __shfl_up(v[R], 1);
+                    const T rv = __shfl_down(v[1], 1);
+                    if (ok && has_left) v[0] = lane == 0 ? X(g + o - 1) : lv;
+                    if (ok && has_right) v[R + 1] = lane == 63 ? X(g + o + R) : rv;
+                }
+            };
 
-    T c[R + 2];
-    load_row(0, true, true, c);
-    T acc[R];
-    // axis 0: second differences with the Neumann ghost at j_0 = M_0; coefficients per node
-    const T* t0 = tab + U.tab[0];
-    T tmix0[R];
+            T c[R + 2];
+            load_row(0, true, true, c);
+            T acc[R];
+            // axis 0: second differences with the Neumann ghost at j_0 = M_0; coefficients per node
+            const T* t0 = tab + U.tab[0];
+            T tmix0[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int jr = j[0] + r;
-        const T xm = c[r];
-        const T xp = (jr == M[0]) ? xm : c[r + 2];
-        acc[r] = t0[jr - 1] * (xp - T(2) * c[r + 1] + xm);
-        tmix0[r] = t0[M[0] + jr - 1];
-    }
-    // axes 1..D-1: rows at -E_k and +E_k (reflected at j_k = M_k), shared coefficients
-    T tmix[D], tphi[D];
-    const T* tV = tab + U.tab[D - 1];
-    const int MV = M[D - 1];
-    const T vsq = tV[j[D - 1] - 1];
-#pragma unroll
-    for (int k = 1; k < D; ++k) {
-        T rm[R + 2], rp[R + 2];
-        const bool up_ok = j[k] != M[k];
-        load_row(-E[k], true, j[k] > 1, rm);
-        load_row(E[k], true, up_ok, rp);
-        if (!up_ok) {
-#pragma unroll
-            for (int r = 0; r < R + 2; ++r) rp[r] = rm[r];
-        }
-        T td;
-        if (k < D - 1) {
-            const T* tk = tab + U.tab[k];
-            td = tk[j[k] - 1];
-            tmix[k] = tk[M[k] + j[k] - 1];
-            tphi[k] = tk[2 * M[k] + j[k] - 1];
-        } else {
-            td = tV[MV];
-            tmix[k] = tV[MV + 1];
-            tphi[k] = T(0);
-        }
-        // advection on axes 1..D-2 (paper axes 2..N-1), zero on the upper face
-        T adv = T(0);
-        if (k < D - 1 && up_ok) {
-#pragma unroll
-            for (int jj = 1; jj <= k; ++jj) adv += cst[CST_RHO + k * MAXD + jj] * tphi[jj];
-            adv *= tmix[k];
-        }
-        const T c0k = (k < D - 1) ? cst[CST_RHO + 0 * MAXD + k] : cst[CST_SPHI + 0];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            acc[r] += td * (rp[r + 1] - T(2) * c[r + 1] + rm[r + 1]);
-            if (k < D - 1 && up_ok) acc[r] += adv * (rp[r + 1] - rm[r + 1]);
-            // mixed (0, k): zero when either node index is on its upper face
-            if (up_ok && (j[0] + r) != M[0]) {
-                const T xx = rp[r + 2] + rm[r] - rp[r] - rm[r + 2];
-                acc[r] += c0k * tmix0[r] * tmix[k] * xx;
+            for (int r = 0; r < R; ++r) {
+                const int jr = j[0] + r;
+                const T xm = c[r];
+                const T xp = (jr == M[0]) ? xm : c[r + 2];
+                acc[r] = t0[jr - 1] * (xp - T(2) * c[r + 1] + xm);
+                tmix0[r] = t0[M[0] + jr - 1];
             }
-        }
-    }
-    // mixed (i, k), 1 <= i < k: four diagonal rows of R nodes
+            // axes 1..D-1: rows at -E_k and +E_k (reflected at j_k = M_k), shared coefficients
+            T tmix[D], tphi[D];
+            const T* tV = tab + U.tab[D - 1];
+            const int MV = M[D - 1];
+            const T vsq = tV[j[D - 1] - 1];
 #pragma unroll
-    for (int i = 1; i < D - 1; ++i) {
+            for (int k = 1; k < D; ++k) {
+                T rm[R + 2], rp[R + 2];
+                const bool up_ok = j[k] != M[k];
+                load_row(-E[k], true, j[k] > 1, rm);
+                load_row(E[k], true, up_ok, rp);
+                if (!up_ok) {
 #pragma unroll
-        for (int k = i + 1; k < D; ++k) {
-            if (j[i] != M[i] && j[k] != M[k]) {
-                T pp[R + 2], mm[R + 2], pm[R + 2], mp[R + 2];
-                load_row(E[i] + E[k], false, true, pp);
-                load_row(-E[i] - E[k], false, j[i] > 1 && j[k] > 1, mm);
-                load_row(E[i] - E[k], false, j[k] > 1, pm);
-                load_row(-E[i] + E[k], false, j[i] > 1, mp);
-                const T cik = ((k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i]) * tmix[i] * tmix[k];
+                    for (int r = 0; r < R + 2; ++r) rp[r] = rm[r];
+                }
+                T td;
+                if (k < D - 1) {
+                    const T* tk = tab + U.tab[k];
+                    td = tk[j[k] - 1];
+                    tmix[k] = tk[M[k] + j[k] - 1];
+                    tphi[k] = tk[2 * M[k] + j[k] - 1];
+                } else {
+                    td = tV[MV];
+                    tmix[k] = tV[MV + 1];
+                    tphi[k] = T(0);
+                }
+                // advection on axes 1..D-2 (paper axes 2..N-1), zero on the upper face
+                T adv = T(0);
+                if (k < D - 1 && up_ok) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += cik * (pp[r + 1] + mm[r + 1] - pm[r + 1] - mp[r + 1]);
+                    for (int jj = 1; jj <= k; ++jj) adv += cst[CST_RHO + k * MAXD + jj] * tphi[jj];
+                    adv *= tmix[k];
+                }
+                const T c0k = (k < D - 1) ? cst[CST_RHO + 0 * MAXD + k] : cst[CST_SPHI + 0];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    acc[r] += td * (rp[r + 1] - T(2) * c[r + 1] + rm[r + 1]);
+                    if (k < D - 1 && up_ok) acc[r] += adv * (rp[r + 1] - rm[r + 1]);
+                    // mixed (0, k): zero when either node index is on its upper face
+                    if (up_ok && (j[0] + r) != M[0]) {
+                        const T xx = rp[r + 2] + rm[r] - rp[r] - rm[r + 2];
+                        acc[r] += c0k * tmix0[r] * tmix[k] * xx;
+                    }
+                }
             }
+            // mixed (i, k), 1 <= i < k: four diagonal rows of R nodes
+#pragma unroll
+            for (int i = 1; i < D - 1; ++i) {
+#pragma unroll
+                for (int k = i + 1; k < D; ++k) {
+                    if (j[i] != M[i] && j[k] != M[k]) {
+                        T pp[R + 2], mm[R + 2], pm[R + 2], mp[R + 2];
+                        load_row(E[i] + E[k], false, true, pp);
+                        load_row(-E[i] - E[k], false, j[i] > 1 && j[k] > 1, mm);
+                        load_row(E[i] - E[k], false, j[k] > 1, pm);
+                        load_row(-E[i] + E[k], false, j[i] > 1, mp);
+                        const T cik = ((k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i]) * tmix[i] * tmix[k];
+#pragma unroll
+                        for (int r = 0; r < R; ++r) acc[r] += cik * (pp[r + 1] + mm[r + 1] - pm[r + 1] - mp[r + 1]);
+                    }
+                }
+            }
+            const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
+            const T* W = (const T*)A.W;
+            const T* cG = (const T*)A.cG;
+            T e[R];
+            if constexpr (OP == OP_STAGE1 || OP == OP_STAGE2) load_vec<T, R>(cG + g, e);
+            if constexpr (OP == OP_REFINE) {
+                load_vec<T, R>(W + g, e);     // K^(0)
+            }
+            T q1[R];
+            if constexpr (OP == OP_STAGE2) load_vec<T, R>(X1 + g, q1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T F = vsq * acc[r];
+                if constexpr (OP == OP_STAGE1) o[r] = sc * (F + e[r]);
+                else if constexpr (OP == OP_STAGE2) o[r] = sc * (F + e[r]) + (T)A.q * q1[r];
+                else o[r] = T(2) * e[r] - c[r + 1] + sc * F;
+            }
+        if (!FUSE || OP != OP_REFINE) store_vec<T, R>((T*)A.W + g, o);
+    }
+    if constexpr (FUSE) {
+        __shared__ T sh[4 * NODE_BLOCK];
+        int s = 0, nseg = 1, M0 = R;
+        const T* f = (const T*)P.fac;
+        if (live) {
+            const UnitDev& U = P.units[u];
+            int SV = 0;
+#pragma unroll
+            for (int k = 0; k < D - 1; ++k) SV += U.lv[k];
+            M0 = 1 << U.lv[0];
+            s = (int)(loc & (M0 - 1)) / R;
+            nseg = M0 / R;
+            const int64_t jv = (loc >> SV) & ((1 << U.lv[D - 1]) - 1);
+            f += (int64_t)U.fac[0] + (int64_t)A.run * P.fac_run_stride + jv * 3 * M0;
         }
+        axis0_segment_solve<T, R>(o, f, M0, s, nseg, live, sh);
+        if (live) store_vec<T, R>((T*)A.S + g, o);
     }
-    const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
-    T* W = (T*)A.W;
-    const T* cG = (const T*)A.cG;
-    T o[R], e[R];
-    if constexpr (OP == OP_STAGE1 || OP == OP_STAGE2) load_vec<T, R>(cG + g, e);
-    if constexpr (OP == OP_REFINE) {
-        load_vec<T, R>(W + g, e);     // K^(0)
-    }
-    T q1[R];
-    if constexpr (OP == OP_STAGE2) load_vec<T, R>(X1 + g, q1);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const T F = vsq * acc[r];
-        if constexpr (OP == OP_STAGE1) o[r] = sc * (F + e[r]);
-        else if constexpr (OP == OP_STAGE2) o[r] = sc * (F + e[r]) + (T)A.q * q1[r];
-        else o[r] = T(2) * e[r] - c[r + 1] + sc * F;
-    }
-    typedef T vt __attribute__((ext_vector_type(R)));
-    vt ov;
-#pragma unroll
-    for (int r = 0; r < R; ++r) ov[r] = o[r];
-    *(vt*)(W + g) = ov;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1133,10 +1278,20 @@ template <typename T, int D, int R>
 static hipError_t stencil_vec(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
     dim3 g((unsigned)P.n_blocks_r[R == 4 ? 2 : 1]), b(NODE_BLOCK);
+    const bool fuse = a.S != nullptr;
     switch (op) {
-    case OP_STAGE1: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R>), g, b, 0, s, P, a); break;
-    case OP_STAGE2: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R>), g, b, 0, s, P, a); break;
-    case OP_REFINE: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R>), g, b, 0, s, P, a); break;
+    case OP_STAGE1:
+        if (fuse) hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R, true>), g, b, 0, s, P, a);
+        else hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R, false>), g, b, 0, s, P, a);
+        break;
+    case OP_STAGE2:
+        if (fuse) hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R, true>), g, b, 0, s, P, a);
+        else hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R, false>), g, b, 0, s, P, a);
+        break;
+    case OP_REFINE:
+        if (fuse) hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R, true>), g, b, 0, s, P, a);
+        else hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R, false>), g, b, 0, s, P, a);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1148,6 +1303,7 @@ static hipError_t stencil_td(const DevPlan& P, int op, const StencilArgs& a, hip
     const bool hot = op == OP_STAGE1 || op == OP_STAGE2 || op == OP_REFINE;
     if (hot && P.stencil_r == 4) return stencil_vec<T, D, 4>(P, op, a, s);
     if (hot && P.stencil_r == 2) return stencil_vec<T, D, 2>(P, op, a, s);
+    if (a.S != nullptr) return hipErrorInvalidValue;     // the fused form needs 2 or 4 nodes per thread
     dim3 g((unsigned)P.n_node_blocks), b(NODE_BLOCK);
     switch (op) {
     case OP_F_PAYOFF: hipLaunchKernelGGL((k_stencil<T, D, OP_F_PAYOFF>), g, b, 0, s, P, a); break;

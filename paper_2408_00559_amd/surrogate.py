@@ -149,11 +149,15 @@ class Mlp:
 
 # ---------------------------------------------------------------------------------------------
 def solver_prices(problems: Sequence[I.Problem], grid, steps: int, precision: str = "fp32",
-                  chunk: int = 512, device: str = "cuda:0") -> np.ndarray:
-    """Prices of `problems` by the solver (batched plans of `chunk` instances, hipGraph replay)."""
+                  chunk: int = 512, device: str = "cuda:0", tune: bool = True) -> np.ndarray:
+    """Prices of `problems` by the solver: batched plans of `chunk` instances, each run with the
+    autotuned schedule (cached per plan shape) and the FP64 combination."""
+    from . import autotune
     out = []
     for s in range(0, len(problems), chunk):
         plan = Plan(problems[s:s + chunk], grid, steps, precision=precision, device=device)
+        if tune:
+            autotune.tune(plan, steps=1, reps=1)
         out.append(plan.price().cpu().numpy())
         del plan
     return np.concatenate(out) if out else np.zeros(0)

@@ -1,12 +1,17 @@
 """Generate solver labels, train the pricing surrogate, calibrate its error estimate and measure
 what it gains over the solver on held-out requests.
 
-    python -m paper_2408_00559_amd.train_surrogate --out <dir> [--train 16384 --cal 4096 --held 8192]
+    # labels (resumable: each set is written chunk by chunk and a rerun continues where it stopped)
+    python -m paper_2408_00559_amd.train_surrogate labels --dir D [--train 200000 --cal 20000 --held 50000]
+                                                         [--max-seconds S]
+    # training, calibration and evaluation from the stored labels
+    python -m paper_2408_00559_amd.train_surrogate train --dir D --out O
 
 Labels: d = 6 (5 rates + V) modified combination technique (psi = 1, level --n), --steps AMFR-W2
-steps, FP32 solver with FP64 combination, instances drawn by inputs.surrogate_instances (seeds 5,
-7 and 6 for training, calibration and held-out sets).  Writes <dir>/surrogate_report.json and
-<dir>/surrogate_weights.pt.
+steps, FP32 solver (autotuned schedule) with FP64 combination, instances drawn by
+inputs.surrogate_instances with seeds 5, 7 and 6 for the training, calibration and held-out sets.
+Only the prices are stored (D/<set>_seed<seed>.npy, float64, NaN = not yet computed): the features
+are re-drawn from the seeds.  `train` writes O/surrogate_report.json and O/surrogate_weights.pt.
 """
 from __future__ import annotations
 
@@ -22,41 +27,68 @@ import torch
 from . import inputs as I
 from . import surrogate as S
 
+SETS = (("train", 5), ("cal", 7), ("held", 6))
 
-def main(argv=None):
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--train", type=int, default=8192)
-    ap.add_argument("--cal", type=int, default=2048)
-    ap.add_argument("--held", type=int, default=4096)
-    ap.add_argument("--n", type=int, default=5)
-    ap.add_argument("--psi", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--epochs", type=int, default=400)
-    ap.add_argument("--batch", type=int, default=1024)
-    ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--out", required=True)
-    a = ap.parse_args(argv)
-    os.makedirs(a.out, exist_ok=True)
-    log = lambda m: print(m, flush=True)
+
+def _label_path(d, name, seed):
+    return os.path.join(d, "%s_seed%d.npy" % (name, seed))
+
+
+def labels(a, log):
+    os.makedirs(a.dir, exist_ok=True)
     grid = I.combination(a.n, a.psi)
-    sets = {}
-    rep = {"labels": {"d": 6, "n": a.n, "psi": a.psi, "steps": a.steps, "precision": "fp32 (FP64 combine)",
-                      "domain": "4x evaluation point"}}
-    for name, count, seed in (("train", a.train, 5), ("cal", a.cal, 7), ("held", a.held, 6)):
+    counts = {"train": a.train, "cal": a.cal, "held": a.held}
+    t_start = time.perf_counter()
+    meta_path = os.path.join(a.dir, "labels_meta.json")
+    meta = json.load(open(meta_path)) if os.path.exists(meta_path) else {}
+    meta.update({"d": 6, "n": a.n, "psi": a.psi, "steps": a.steps, "chunk": a.chunk,
+                 "precision": "fp32 (FP64 combine)", "domain": "4x evaluation point"})
+    for name, seed in SETS:
+        count = counts[name]
+        path = _label_path(a.dir, name, seed)
+        y = np.load(path) if os.path.exists(path) else np.full(count, np.nan)
+        if len(y) < count:
+            y = np.concatenate([y, np.full(count - len(y), np.nan)])
         probs = I.surrogate_instances(count, seed)
-        torch.cuda.synchronize()
+        todo = [s for s in range(0, count, a.chunk) if np.isnan(y[s:s + a.chunk]).any()]
+        done_before = int(np.sum(~np.isnan(y)))
         t0 = time.perf_counter()
-        y = S.solver_prices(probs, grid, a.steps)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        for s in todo:
+            if a.max_seconds and time.perf_counter() - t_start > a.max_seconds:
+                log("time budget reached; %s has %d of %d labels" % (name, int(np.sum(~np.isnan(y))), count))
+                np.save(path, y)
+                json.dump(meta, open(meta_path, "w"), indent=1)
+                return 3
+            e = min(count, s + a.chunk)
+            y[s:e] = S.solver_prices(probs[s:e], grid, a.steps, chunk=a.chunk, tune=True)
+            np.save(path, y)
+            log("labels %s: %d / %d (%.0f prices/s)" % (name, e, count,
+                (int(np.sum(~np.isnan(y))) - done_before) / max(time.perf_counter() - t0, 1e-9)))
+        if todo:
+            meta.setdefault("rates", {})[name] = (int(np.sum(~np.isnan(y))) - done_before) / (time.perf_counter() - t0)
+        json.dump(meta, open(meta_path, "w"), indent=1)
+    return 0
+
+
+def train(a, log):
+    os.makedirs(a.out, exist_ok=True)
+    meta = json.load(open(os.path.join(a.dir, "labels_meta.json")))
+    grid = I.combination(meta["n"], meta["psi"])
+    steps = meta["steps"]
+    sets = {}
+    for name, seed in SETS:
+        y = np.load(_label_path(a.dir, name, seed))
+        if np.isnan(y).any():
+            raise RuntimeError("labels of %s are incomplete" % name)
+        probs = I.surrogate_instances(len(y), seed)
         sets[name] = (probs, S.features(probs), y)
-        rep["labels"][name] = {"count": count, "seconds": dt, "solver_prices_per_s": count / dt}
-        log("labels %s: %d in %.1f s (%.0f prices/s)" % (name, count, dt, count / dt))
+    rep = {"labels": dict(meta, counts={k: len(v[2]) for k, v in sets.items()})}
     _, xtr, ytr = sets["train"]
     t0 = time.perf_counter()
-    sur = S.Surrogate.train(xtr, ytr, grid, a.steps, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
+    sur = S.Surrogate.train(xtr, ytr, grid, steps, epochs=a.epochs, batch=a.batch, lr=a.lr, log=log)
     torch.cuda.synchronize()
     rep["training"] = {"seconds": time.perf_counter() - t0, "epochs": a.epochs, "batch": a.batch, "lr": a.lr,
+                       "target": "log price" if sur.mlp.norm[4] else "price",
                        "network": "8 -> 256 -> 256 -> 256 -> 2, SiLU, BF16 weights/activations, FP32 accumulate"}
     _, xc, yc = sets["cal"]
     rep["calibration"] = {"factor": sur.calibrate(xc, yc), "quantile": 0.95}
@@ -71,36 +103,66 @@ def main(argv=None):
         out = sur.mlp.forward(xt)
     torch.cuda.synchronize()
     t_net = (time.perf_counter() - t0) / reps
-    p, err = out[:, 0].double().cpu().numpy(), out[:, 1].double().cpu().numpy()
+    p = out[:, 0].double().cpu().numpy()
     rel = np.abs(p - yh) / np.abs(yh)
-    rep["held_out"] = {"count": len(yh), "network_prices_per_s": len(yh) / t_net,
-                       "network_seconds": t_net,
+    solver_rate = meta.get("rates", {}).get("held")
+    rep["held_out"] = {"count": len(yh), "network_prices_per_s": len(yh) / t_net, "network_seconds": t_net,
                        "rel_err": {"median": float(np.median(rel)), "p90": float(np.quantile(rel, 0.9)),
                                    "p99": float(np.quantile(rel, 0.99)), "max": float(rel.max())},
-                       "solver_prices_per_s": rep["labels"]["held"]["solver_prices_per_s"]}
+                       "solver_prices_per_s": solver_rate}
+    # serving with fallback on a held-out sample (the solver prices every routed request again)
+    ns = min(len(hp), a.serve_sample)
     rows = []
     for tol in (1e-4, 1e-3, 1e-2, 3e-2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pp, used, tn, tf = sur.price(hp, tol=tol)
+        pp, used, tn, tf = sur.price(hp[:ns], tol=tol)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        r = np.abs(pp - yh) / np.abs(yh)
+        r = np.abs(pp - yh[:ns]) / np.abs(yh[:ns])
         served = ~used
-        rows.append({"tol": tol, "served_fraction": float(served.mean()),
+        rows.append({"tol": tol, "requests": ns, "served_fraction": float(served.mean()),
                      "served_rel_err_max": float(r[served].max()) if served.any() else None,
                      "served_rel_err_p95": float(np.quantile(r[served], 0.95)) if served.any() else None,
                      "within_tol_fraction_of_served": float(np.mean(r[served] <= tol)) if served.any() else None,
-                     "prices_per_s_with_fallback": len(hp) / dt, "seconds": dt})
+                     "prices_per_s_with_fallback": ns / dt, "seconds": dt,
+                     "speedup_vs_solver": (ns / dt) / solver_rate if solver_rate else None})
         log("tol %.0e: served %.1f%% p95 %s, %.0f prices/s" % (tol, 100 * served.mean(),
-            rows[-1]["served_rel_err_p95"], len(hp) / dt))
+            rows[-1]["served_rel_err_p95"], ns / dt))
     rep["fallback"] = rows
     torch.save({"params": sur.mlp.params().cpu(), "norm": sur.mlp.norm, "calib": sur.calib,
                 "box_lo": sur.box_lo, "box_hi": sur.box_hi, "layout": sur.mlp.layout(),
-                "grid": {"n": a.n, "psi": a.psi}, "steps": a.steps}, os.path.join(a.out, "surrogate_weights.pt"))
+                "grid": {"n": meta["n"], "psi": meta["psi"]}, "steps": steps},
+               os.path.join(a.out, "surrogate_weights.pt"))
     json.dump(rep, open(os.path.join(a.out, "surrogate_report.json"), "w"), indent=1)
     log(json.dumps(rep))
     return 0
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("mode", choices=["labels", "train"])
+    ap.add_argument("--dir", required=True, help="label directory")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--train", type=int, default=200000)
+    ap.add_argument("--cal", type=int, default=20000)
+    ap.add_argument("--held", type=int, default=50000)
+    ap.add_argument("--n", type=int, default=5)
+    ap.add_argument("--psi", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--chunk", type=int, default=512)
+    ap.add_argument("--max-seconds", type=float, default=0.0)
+    ap.add_argument("--epochs", type=int, default=200)
+    ap.add_argument("--batch", type=int, default=2048)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--serve-sample", type=int, default=4096)
+    a = ap.parse_args(argv)
+    log = lambda m: print(m, flush=True)
+    if a.mode == "labels":
+        return labels(a, log)
+    if not a.out:
+        ap.error("train needs --out")
+    return train(a, log)
 
 
 if __name__ == "__main__":

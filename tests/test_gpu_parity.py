@@ -335,3 +335,43 @@ def test_resident_schedule(name, precision, tol):
     plan.use_graph(True)
     p_res = plan.price().cpu().numpy()
     assert np.allclose(p_res, p_stream, rtol=1e-12 if precision == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("name", ["fg2d", "long_rate_axis", "d3_full_ragged", "d2_standard_ct", "d3_ct",
+                                  "d4_ct", "d6_ct"])
+def test_fused_axis0_schedule(name, precision, tol):
+    """a3+a4: operator launches that also solve the axis-1 systems of the first AMF factor in the
+    block (segments of consecutive threads joined by a scan), against the oracle after two steps,
+    and a whole solve against the unfused schedule."""
+    probs, grid = CASES[name]
+    steps = 5
+    plan = Plan(probs, grid, steps=steps, precision=precision, device=DEV)
+    rs = [r for r in (4, 2) if r <= plan.schedule()["max_stencil_nodes"] and plan.fuse_allowed(r)]
+    if not rs:
+        pytest.skip("no operator width admits the fused axis-0 solve")
+    items = unit_slices(plan)
+
+    def ref(item):
+        u, sl = item
+        p = probs[u["problem"]]
+        lv = u["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / steps, 2)
+        return oracle.inner_view(Yf, lv)
+
+    refs = parallel(ref, items)
+    plan.set_schedule(fuse_axis0=0)
+    p_plain = plan.price().cpu().numpy()
+    for r in rs:
+        plan.set_schedule(stencil_nodes=r, fuse_axis0=1, resident=0)
+        plan.init()
+        plan.time_step(2)
+        Y = plan.state().cpu().numpy().astype(np.float64)
+        for (u, sl), rr in zip(items, refs):
+            t = max(tol, 4e-16 * (1 << max(u["levels"]))) if precision == "fp64" else tol
+            assert rel_maxerr(Y[sl], rr) < t, (r, u, rel_maxerr(Y[sl], rr))
+        plan.use_graph(True)
+        p_fused = plan.price().cpu().numpy()
+        plan.use_graph(False)
+        assert np.allclose(p_fused, p_plain, rtol=1e-12 if precision == "fp64" else 1e-5), r

@@ -34,6 +34,19 @@ def test_forward_matches_reference():
     assert np.max(np.abs(np.log(out[:, 1]) - np.log(err))) < 2e-2
 
 
+def test_forward_log_target_matches_reference():
+    """Log-price target mode: price = exp(y0 s + m), relative error estimate = exp(y1) s."""
+    net, lay, x, mean, std = _setup(seed=4)
+    net.set_normalization(mean, std, -4.0, 0.5, out_log=True)
+    out = net.forward(torch.tensor(x)).cpu().numpy()
+    p = net.params().cpu().numpy().astype(np.float64)
+    y, _ = M.forward(lay, p, x, mean, std, bf16=True)
+    price = np.exp(y[:, 0] * 0.5 - 4.0)
+    err = np.exp(y[:, 1]) * 0.5
+    assert np.max(np.abs(out[:, 0] - price) / price) < 2e-3
+    assert np.max(np.abs(np.log(out[:, 1]) - np.log(err))) < 2e-2
+
+
 def test_gradients_match_reference():
     net, lay, x, mean, std = _setup(seed=5, B=96)
     rng = np.random.default_rng(7)
