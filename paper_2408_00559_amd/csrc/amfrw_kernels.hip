@@ -356,151 +356,151 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
     // ~50 VGPRs here: its lambdas lose track of which values are wave-uniform)
     if (live) {
         const UnitDev U = P.units[u];
-            const ProbDev& PR = P.probs[U.prob];
-            const T* tab = (const T*)P.tab;
-            const T* cst = tab + PR.cst;
+        const ProbDev& PR = P.probs[U.prob];
+        const T* tab = (const T*)P.tab;
+        const T* cst = tab + PR.cst;
 
-            int j[D], M[D];
-            int64_t E[D];
-            {
-                int sh = 0;
+        int j[D], M[D];
+        int64_t E[D];
+        {
+            int sh = 0;
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    M[i] = 1 << U.lv[i];
-                    E[i] = (int64_t)1 << sh;
-                    j[i] = (int)((loc >> sh) & (M[i] - 1)) + 1;   // j[0] = first of the R nodes
-                    sh += U.lv[i];
-                }
+            for (int i = 0; i < D; ++i) {
+                M[i] = 1 << U.lv[i];
+                E[i] = (int64_t)1 << sh;
+                j[i] = (int)((loc >> sh) & (M[i] - 1)) + 1;   // j[0] = first of the R nodes
+                sh += U.lv[i];
             }
-            const T* X0 = (const T*)A.X0;
-            const T* X1 = (const T*)A.X1;
-            const T av = (T)A.a;
-            const bool has_left = j[0] > 1, has_right = j[0] + R - 1 < M[0];
-            const int lane = threadIdx.x & 63;
-            auto X = [&](int64_t idx) -> T {
-                if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
-                else return X0[idx];
-            };
-            // v[1..R]: the row of R nodes at offset o (0 where !ok).  With `ends` (wave-uniform: every
-            // active lane must reach the shuffles) also v[0], v[R+1]: the axis-0 neighbours, taken from
-            // the adjacent lanes' rows (lanes hold consecutive R-node chunks), loaded only by the lanes
-            // at the wave's edges, 0 on the lower face and beyond the line's end.
-            auto load_row = [&](int64_t o, bool ends, bool ok, T* v) {
-                if (ok) {
-                    load_vec<T, R>(X0 + g + o, v + 1);
-                    if constexpr (OP == OP_STAGE2) {
-                        T w[R];
-                        load_vec<T, R>(X1 + g + o, w);
+        }
+        const T* X0 = (const T*)A.X0;
+        const T* X1 = (const T*)A.X1;
+        const T av = (T)A.a;
+        const bool has_left = j[0] > 1, has_right = j[0] + R - 1 < M[0];
+        const int lane = threadIdx.x & 63;
+        auto X = [&](int64_t idx) -> T {
+            if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
+            else return X0[idx];
+        };
+        // v[1..R]: the row of R nodes at offset o (0 where !ok).  With `ends` (wave-uniform: every
+        // active lane must reach the shuffles) also v[0], v[R+1]: the axis-0 neighbours, taken from
+        // the adjacent lanes' rows (lanes hold consecutive R-node chunks), loaded only by the lanes
+        // at the wave's edges, 0 on the lower face and beyond the line's end.
+        auto load_row = [&](int64_t o, bool ends, bool ok, T* v) {
+            if (ok) {
+                load_vec<T, R>(X0 + g + o, v + 1);
+                if constexpr (OP == OP_STAGE2) {
+                    T w[R];
+                    load_vec<T, R>(X1 + g + o, w);
 #pragma unroll
-                        for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
-                    }
-                } else {
+                    for (int r = 0; r < R; ++r) v[1 + r] += av * w[r];
+                }
+            } else {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) v[1 + r] = T(0);
-                }
-                v[0] = T(0);
-                v[R + 1] = T(0);
-                if (ends) {
-                    const T lv = __shfl_up(v[R], 1);
-                    const T rv = __shfl_down(v[1], 1);
-                    if (ok && has_left) v[0] = lane == 0 ? X(g + o - 1) : lv;
-                    if (ok && has_right) v[R + 1] = lane == 63 ? X(g + o + R) : rv;
-                }
-            };
+                for (int r = 0; r < R; ++r) v[1 + r] = T(0);
+            }
+            v[0] = T(0);
+            v[R + 1] = T(0);
+            if (ends) {
+                const T lv = __shfl_up(v[R], 1);
+                const T rv = __shfl_down(v[1], 1);
+                if (ok && has_left) v[0] = lane == 0 ? X(g + o - 1) : lv;
+                if (ok && has_right) v[R + 1] = lane == 63 ? X(g + o + R) : rv;
+            }
+        };
 
-            T c[R + 2];
-            load_row(0, true, true, c);
-            T acc[R];
-            // axis 0: second differences with the Neumann ghost at j_0 = M_0; coefficients per node
-            const T* t0 = tab + U.tab[0];
-            T tmix0[R];
+        T c[R + 2];
+        load_row(0, true, true, c);
+        T acc[R];
+        // axis 0: second differences with the Neumann ghost at j_0 = M_0; coefficients per node
+        const T* t0 = tab + U.tab[0];
+        T tmix0[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int jr = j[0] + r;
+            const T xm = c[r];
+            const T xp = (jr == M[0]) ? xm : c[r + 2];
+            acc[r] = t0[jr - 1] * (xp - T(2) * c[r + 1] + xm);
+            tmix0[r] = t0[M[0] + jr - 1];
+        }
+        // axes 1..D-1: rows at -E_k and +E_k (reflected at j_k = M_k), shared coefficients
+        T tmix[D], tphi[D];
+        const T* tV = tab + U.tab[D - 1];
+        const int MV = M[D - 1];
+        const T vsq = tV[j[D - 1] - 1];
+#pragma unroll
+        for (int k = 1; k < D; ++k) {
+            T rm[R + 2], rp[R + 2];
+            const bool up_ok = j[k] != M[k];
+            load_row(-E[k], true, j[k] > 1, rm);
+            load_row(E[k], true, up_ok, rp);
+            if (!up_ok) {
+#pragma unroll
+                for (int r = 0; r < R + 2; ++r) rp[r] = rm[r];
+            }
+            T td;
+            if (k < D - 1) {
+                const T* tk = tab + U.tab[k];
+                td = tk[j[k] - 1];
+                tmix[k] = tk[M[k] + j[k] - 1];
+                tphi[k] = tk[2 * M[k] + j[k] - 1];
+            } else {
+                td = tV[MV];
+                tmix[k] = tV[MV + 1];
+                tphi[k] = T(0);
+            }
+            // advection on axes 1..D-2 (paper axes 2..N-1), zero on the upper face
+            T adv = T(0);
+            if (k < D - 1 && up_ok) {
+#pragma unroll
+                for (int jj = 1; jj <= k; ++jj) adv += cst[CST_RHO + k * MAXD + jj] * tphi[jj];
+                adv *= tmix[k];
+            }
+            const T c0k = (k < D - 1) ? cst[CST_RHO + 0 * MAXD + k] : cst[CST_SPHI + 0];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const int jr = j[0] + r;
-                const T xm = c[r];
-                const T xp = (jr == M[0]) ? xm : c[r + 2];
-                acc[r] = t0[jr - 1] * (xp - T(2) * c[r + 1] + xm);
-                tmix0[r] = t0[M[0] + jr - 1];
-            }
-            // axes 1..D-1: rows at -E_k and +E_k (reflected at j_k = M_k), shared coefficients
-            T tmix[D], tphi[D];
-            const T* tV = tab + U.tab[D - 1];
-            const int MV = M[D - 1];
-            const T vsq = tV[j[D - 1] - 1];
-#pragma unroll
-            for (int k = 1; k < D; ++k) {
-                T rm[R + 2], rp[R + 2];
-                const bool up_ok = j[k] != M[k];
-                load_row(-E[k], true, j[k] > 1, rm);
-                load_row(E[k], true, up_ok, rp);
-                if (!up_ok) {
-#pragma unroll
-                    for (int r = 0; r < R + 2; ++r) rp[r] = rm[r];
-                }
-                T td;
-                if (k < D - 1) {
-                    const T* tk = tab + U.tab[k];
-                    td = tk[j[k] - 1];
-                    tmix[k] = tk[M[k] + j[k] - 1];
-                    tphi[k] = tk[2 * M[k] + j[k] - 1];
-                } else {
-                    td = tV[MV];
-                    tmix[k] = tV[MV + 1];
-                    tphi[k] = T(0);
-                }
-                // advection on axes 1..D-2 (paper axes 2..N-1), zero on the upper face
-                T adv = T(0);
-                if (k < D - 1 && up_ok) {
-#pragma unroll
-                    for (int jj = 1; jj <= k; ++jj) adv += cst[CST_RHO + k * MAXD + jj] * tphi[jj];
-                    adv *= tmix[k];
-                }
-                const T c0k = (k < D - 1) ? cst[CST_RHO + 0 * MAXD + k] : cst[CST_SPHI + 0];
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    acc[r] += td * (rp[r + 1] - T(2) * c[r + 1] + rm[r + 1]);
-                    if (k < D - 1 && up_ok) acc[r] += adv * (rp[r + 1] - rm[r + 1]);
-                    // mixed (0, k): zero when either node index is on its upper face
-                    if (up_ok && (j[0] + r) != M[0]) {
-                        const T xx = rp[r + 2] + rm[r] - rp[r] - rm[r + 2];
-                        acc[r] += c0k * tmix0[r] * tmix[k] * xx;
-                    }
+                acc[r] += td * (rp[r + 1] - T(2) * c[r + 1] + rm[r + 1]);
+                if (k < D - 1 && up_ok) acc[r] += adv * (rp[r + 1] - rm[r + 1]);
+                // mixed (0, k): zero when either node index is on its upper face
+                if (up_ok && (j[0] + r) != M[0]) {
+                    const T xx = rp[r + 2] + rm[r] - rp[r] - rm[r + 2];
+                    acc[r] += c0k * tmix0[r] * tmix[k] * xx;
                 }
             }
-            // mixed (i, k), 1 <= i < k: four diagonal rows of R nodes
+        }
+        // mixed (i, k), 1 <= i < k: four diagonal rows of R nodes
 #pragma unroll
-            for (int i = 1; i < D - 1; ++i) {
+        for (int i = 1; i < D - 1; ++i) {
 #pragma unroll
-                for (int k = i + 1; k < D; ++k) {
-                    if (j[i] != M[i] && j[k] != M[k]) {
-                        T pp[R + 2], mm[R + 2], pm[R + 2], mp[R + 2];
-                        load_row(E[i] + E[k], false, true, pp);
-                        load_row(-E[i] - E[k], false, j[i] > 1 && j[k] > 1, mm);
-                        load_row(E[i] - E[k], false, j[k] > 1, pm);
-                        load_row(-E[i] + E[k], false, j[i] > 1, mp);
-                        const T cik = ((k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i]) * tmix[i] * tmix[k];
+            for (int k = i + 1; k < D; ++k) {
+                if (j[i] != M[i] && j[k] != M[k]) {
+                    T pp[R + 2], mm[R + 2], pm[R + 2], mp[R + 2];
+                    load_row(E[i] + E[k], false, true, pp);
+                    load_row(-E[i] - E[k], false, j[i] > 1 && j[k] > 1, mm);
+                    load_row(E[i] - E[k], false, j[k] > 1, pm);
+                    load_row(-E[i] + E[k], false, j[i] > 1, mp);
+                    const T cik = ((k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i]) * tmix[i] * tmix[k];
 #pragma unroll
-                        for (int r = 0; r < R; ++r) acc[r] += cik * (pp[r + 1] + mm[r + 1] - pm[r + 1] - mp[r + 1]);
-                    }
+                    for (int r = 0; r < R; ++r) acc[r] += cik * (pp[r + 1] + mm[r + 1] - pm[r + 1] - mp[r + 1]);
                 }
             }
-            const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
-            const T* W = (const T*)A.W;
-            const T* cG = (const T*)A.cG;
-            T e[R];
-            if constexpr (OP == OP_STAGE1 || OP == OP_STAGE2) load_vec<T, R>(cG + g, e);
-            if constexpr (OP == OP_REFINE) {
-                load_vec<T, R>(W + g, e);     // K^(0)
-            }
-            T q1[R];
-            if constexpr (OP == OP_STAGE2) load_vec<T, R>(X1 + g, q1);
+        }
+        const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
+        const T* W = (const T*)A.W;
+        const T* cG = (const T*)A.cG;
+        T e[R];
+        if constexpr (OP == OP_STAGE1 || OP == OP_STAGE2) load_vec<T, R>(cG + g, e);
+        if constexpr (OP == OP_REFINE) {
+            load_vec<T, R>(W + g, e);     // K^(0)
+        }
+        T q1[R];
+        if constexpr (OP == OP_STAGE2) load_vec<T, R>(X1 + g, q1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const T F = vsq * acc[r];
-                if constexpr (OP == OP_STAGE1) o[r] = sc * (F + e[r]);
-                else if constexpr (OP == OP_STAGE2) o[r] = sc * (F + e[r]) + (T)A.q * q1[r];
-                else o[r] = T(2) * e[r] - c[r + 1] + sc * F;
-            }
+        for (int r = 0; r < R; ++r) {
+            const T F = vsq * acc[r];
+            if constexpr (OP == OP_STAGE1) o[r] = sc * (F + e[r]);
+            else if constexpr (OP == OP_STAGE2) o[r] = sc * (F + e[r]) + (T)A.q * q1[r];
+            else o[r] = T(2) * e[r] - c[r + 1] + sc * F;
+        }
         if (!FUSE || OP != OP_REFINE) store_vec<T, R>((T*)A.W + g, o);
     }
     if constexpr (FUSE) {
