@@ -106,9 +106,14 @@ def train(a, log):
     p = out[:, 0].double().cpu().numpy()
     rel = np.abs(p - yh) / np.abs(yh)
     solver_rate = meta.get("rates", {}).get("held")
+    ab = np.abs(p - yh)
     rep["held_out"] = {"count": len(yh), "network_prices_per_s": len(yh) / t_net, "network_seconds": t_net,
                        "rel_err": {"median": float(np.median(rel)), "p90": float(np.quantile(rel, 0.9)),
                                    "p99": float(np.quantile(rel, 0.99)), "max": float(rel.max())},
+                       "abs_err": {"median": float(np.median(ab)), "p90": float(np.quantile(ab, 0.9)),
+                                   "p99": float(np.quantile(ab, 0.99)), "max": float(ab.max())},
+                       "label_price": {"median": float(np.median(yh)), "min": float(yh.min()),
+                                       "max": float(yh.max()), "nonpositive": int(np.sum(yh <= 0))},
                        "solver_prices_per_s": solver_rate}
     # serving with fallback on a held-out sample (the solver prices every routed request again)
     ns = min(len(hp), a.serve_sample)
