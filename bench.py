@@ -254,6 +254,52 @@ def run_ct6(torch, Plan):
     return res
 
 
+def run_surrogate(torch, Plan):
+    """Form (4) next to the solver on the surrogate's label discretisation (d = 6, n = 5, psi = 1,
+    100 steps, FP32 with FP64 combine): solver prices/s on 512 seeded requests, the BF16-MFMA
+    network's prices/s on 50,000 requests (throughput does not depend on the weights), and the
+    held-out accuracy and fallback rates of the trained network as recorded in
+    profiles/surrogate_d6_n5.json by train_surrogate."""
+    from paper_2408_00559_amd import autotune
+    from paper_2408_00559_amd import inputs as I
+    from paper_2408_00559_amd import surrogate as S
+
+    w = I.workload_surrogate_labels(512, 6)
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp32", device="cuda:0")
+    autotune.tune(plan, steps=1, reps=1)
+    plan.use_graph(True)
+    plan.price()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.price()
+    torch.cuda.synchronize()
+    solver_rate = len(w["problems"]) / (time.perf_counter() - t0)
+    del plan
+    torch.cuda.empty_cache()
+    net = S.Mlp(n_in=8, width=256, depth=3, max_batch=50000, seed=1)
+    x = torch.randn(50000, 8, dtype=torch.float32, device="cuda:0")
+    net.set_normalization([0.0] * 8, [1.0] * 8, 0.02, 0.01)
+    net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        net.forward(x)
+    torch.cuda.synchronize()
+    net_rate = 10 * 50000 / (time.perf_counter() - t0)
+    res = {"workload": "surrogate labels d6 n5 psi1 100 steps", "solver_prices_per_s": solver_rate,
+           "network_prices_per_s": net_rate, "network_flop_per_price": 2 * (8 * 256 + 2 * 256 * 256 + 256 * 2)}
+    rep_path = os.path.join(ROOT, "profiles", "surrogate_d6_n5.json")
+    if os.path.exists(rep_path):
+        rep = json.load(open(rep_path))
+        res["trained"] = {"labels": rep.get("labels", {}).get("counts"),
+                          "held_out_rel_err": rep.get("held_out", {}).get("rel_err"),
+                          "fallback": [{k: r.get(k) for k in ("tol", "served_fraction", "served_rel_err_p95",
+                                                              "prices_per_s_with_fallback")}
+                                       for r in rep.get("fallback", [])],
+                          "source": "profiles/surrogate_d6_n5.json"}
+    return res
+
+
 def cpu_baseline(w, max_seconds_hint=20.0):
     """The FP64 oracle on a bounded sample of the same workload: the smallest combination layer
     (35 component grids of 65,536 inner points) for a few of the 100 time steps, all host cores."""
@@ -315,6 +361,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-ct6", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/hbm_traffic_ct4.json from two rocprofv3 --pmc runs")
     ap.add_argument("--pmc-precision", default="fp64")
@@ -383,6 +430,8 @@ def main():
         res["serving_batch4"] = run_serving(torch, Plan)
     if not args.no_ct6:
         res["ct6_fp32_richardson"] = run_ct6(torch, Plan)
+    if not args.no_surrogate:
+        res["surrogate"] = run_surrogate(torch, Plan)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)
