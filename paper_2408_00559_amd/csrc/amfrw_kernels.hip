@@ -530,14 +530,30 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
 // The matrix of a line depends only on (problem, axis, M_axis, j_V) and dt, so strided axes use
 // Thomas factors (inv_r = 1/pivot_r, a_r inv_r, c'_r) tabulated once per plan in FP64.
 
+// Grid vectors are streamed once per sweep: in FP64 loads and stores carry the non-temporal hint
+// (measured faster there, slower in FP32).
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T* p)
+{
+    if constexpr (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+
+template <typename T>
+__device__ __forceinline__ void st_stream(T* p, T v)
+{
+    if constexpr (sizeof(T) == 8) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 template <typename T, int EPI>
 __device__ __forceinline__ void sweep_store(const SweepArgs& A, int64_t idx, T x)
 {
     if constexpr (EPI == EPI_STORE) {
-        ((T*)A.out)[idx] = x;
+        st_stream((T*)A.out + idx, x);
     } else {
         T* W = (T*)A.out;
-        W[idx] = W[idx] + (T)A.b1 * ((const T*)A.K1)[idx] + (T)A.b2 * x;
+        st_stream(W + idx, ld_stream(W + idx) + (T)A.b1 * ld_stream((const T*)A.K1 + idx) + (T)A.b2 * x);
     }
 }
 
@@ -579,7 +595,7 @@ __device__ __forceinline__ void sweep_strided_reg(const DevPlan& P, const SweepA
     T dp[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-        const T G = in[L.base + r * L.stride];
+        const T G = ld_stream(in + L.base + r * L.stride);
         dp[r] = (r == 0) ? G * f[0] : G * f[r] - f[M + r] * dp[r - 1];
     }
     T x = dp[M - 1];
@@ -700,7 +716,7 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
     if (live) {
         const T* in = (const T*)A.in;
 #pragma unroll
-        for (int k = 0; k < SSEG; ++k) v[k] = in[L.base + (int64_t)(r0 + k) * L.stride];
+        for (int k = 0; k < SSEG; ++k) v[k] = ld_stream(in + L.base + (int64_t)(r0 + k) * L.stride);
 #pragma unroll
         for (int k = 0; k < SSEG; ++k) {
             const T ai = f[M + r0 + k];
