@@ -56,6 +56,7 @@ struct amf_plan {
     std::vector<int64_t> ax_line_off[MAXD];
     std::vector<SweepBlk> ax_blk[MAXD];
     double ax_short_frac[MAXD]{};          // share of inner points on lines up to 2^SHORT_LM
+    int ax_vec[MAXD]{};                    // lines per thread of the short strided sweep (1 or 16 B / elem)
     int64_t total = 0;                     // elements per grid vector (with alignment padding)
     int64_t inner = 0;                     // inner points over all units
 
@@ -469,6 +470,16 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             for (int u = 0; u < P->n_units; ++u)
                 if (P->units[u].lv[ax] <= SHORT_LM) short_pts += (int64_t)1 << P->units[u].lsum;
             P->ax_short_frac[ax] = P->inner > 0 ? (double)short_pts / (double)P->inner : 0.0;
+            // strided lines: a thread (short lines) or a segment slot (long lines) takes V = 16 B / elem
+            // adjacent lines, one vector per row, when every unit has runs of at least V adjacent
+            // lines on this axis
+            int vec = ax > 0 ? 16 / (int)P->elem : 1;
+            for (int u = 0; u < P->n_units && vec > 1; ++u) {
+                int S = 0;
+                for (int i = 0; i < ax; ++i) S += P->units[u].lv[i];
+                if ((1 << S) < vec) vec = 1;
+            }
+            P->ax_vec[ax] = vec;
             int k0 = 0;
             while (k0 < P->n_units) {
                 const int lm = P->units[ord[k0]].lv[ax];
@@ -476,12 +487,12 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 while (k1 < P->n_units && P->units[ord[k1]].lv[ax] == lm) ++k1;
                 int k = k0;
                 // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each
-                // longer strided lines: M/sseg threads each in blocks of SEG_BLOCK threads
-                int per = LINE_BLOCK;
-                const int ss = precision == AMF_FP64 ? SSEG_F64 : SSEG_F32;
+                // longer strided lines: M/seg_rows threads per line slot in blocks of SEG_BLOCK threads
+                int per = LINE_BLOCK * (ax > 0 && lm <= SHORT_LM ? vec : 1);
+                const int ss = seg_rows((int)P->elem, vec);
                 if (ax == 0 && lm > CONTIG_REG_LM) per = LINE_BLOCK / ((1 << lm) / SEG);
                 else if (ax > 0 && lm > SHORT_LM)
-                    per = lm <= seg_max_lm((int)P->elem) ? (SEG_BLOCK * ss) >> lm : SEG_BLOCK;
+                    per = lm <= seg_max_lm((int)P->elem, vec) ? ((SEG_BLOCK * ss) >> lm) * vec : SEG_BLOCK;
                 for (int64_t s = lo[k0]; s < lo[k1]; s += per) {
                     while (s >= lo[k + 1]) ++k;
                     SweepBlk B{};
@@ -629,6 +640,7 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
         int64_t ns = 0;
         while (ns < D.ax_nblk[ax] && P->ax_blk[ax][ns].lm <= SHORT_LM) ++ns;
         D.ax_nblk_short[ax] = ns;
+        D.ax_vec[ax] = P->ax_vec[ax];
     }
     P->bound = true;
     return AMF_OK;

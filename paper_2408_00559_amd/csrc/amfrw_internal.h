@@ -13,16 +13,23 @@ constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
 // Longest strided line kept whole in VGPRs by one thread (log2) in the short-line launch.
 constexpr int REG_LM = 5;
-// Longer strided lines: sseg(T) consecutive rows per thread (8 in FP64, 32 in FP32; measured on
-// the d = 4 workload), M/sseg threads per line, blocks of SEG_BLOCK threads (SEG_BLOCK*sseg/M
-// lines each), up to SEG_BLOCK*sseg rows; beyond that one thread per line streams through memory
-// in chunks of CHUNK rows.
+// Longer strided lines: seg_rows consecutive rows per thread (one line: 8 in FP64, 32 in FP32;
+// measured on the d = 4 workload), M/seg_rows threads per line, blocks of SEG_BLOCK threads
+// (SEG_BLOCK*seg_rows/M line slots each), up to SEG_BLOCK*seg_rows rows; beyond that one thread
+// per line streams through memory in chunks of CHUNK rows.
 constexpr int SSEG_F64 = 8;
 constexpr int SSEG_F32 = 32;
 constexpr int SEG_BLOCK = 512;
-template <typename T> constexpr int sseg() { return sizeof(T) == 8 ? SSEG_F64 : SSEG_F32; }
-// log2 of the longest line the segmented solver takes, by element size
-constexpr int seg_max_lm(int elem) { return elem == 8 ? 12 : 14; }
+// rows per thread by element size and by lines per thread (vec > 1: vec adjacent lines carried as
+// one vector: 128 bytes of line data per thread)
+constexpr int seg_rows(int elem, int vec) { return vec > 1 ? 128 / (vec * elem) : (elem == 8 ? SSEG_F64 : SSEG_F32); }
+// log2 of the longest line the segmented solver takes: SEG_BLOCK * seg_rows rows
+constexpr int seg_max_lm(int elem, int vec)
+{
+    int r = SEG_BLOCK * seg_rows(elem, vec), l = 0;
+    while (r > 1) { r >>= 1; ++l; }
+    return l;
+}
 constexpr int CHUNK = 4;
 constexpr int NXCD = 8;
 // Default nodes per thread of the time-loop operator, by precision (limited by each unit's M_0);
@@ -99,6 +106,7 @@ struct DevPlan {
     const SweepBlk* ax_blk[MAXD];
     int64_t ax_nblk[MAXD];
     int64_t ax_nblk_short[MAXD];       // leading blocks with lm <= SHORT_LM
+    int ax_vec[MAXD];                  // short strided lines: 16-byte vectors of adjacent lines per thread
 };
 
 // Stencil operation selector.  Solution vectors are stored as W = Y - g (zero on every lower face);

@@ -533,16 +533,21 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
 // Grid vectors are streamed once per sweep: in FP64 loads and stores carry the non-temporal hint
 // (measured faster there, slower in FP32).
 template <typename T>
+struct elem_of { using type = T; };
+template <typename T, int N>
+struct elem_of<T __attribute__((ext_vector_type(N)))> { using type = T; };
+
+template <typename T>
 __device__ __forceinline__ T ld_stream(const T* p)
 {
-    if constexpr (sizeof(T) == 8) return __builtin_nontemporal_load(p);
+    if constexpr (sizeof(typename elem_of<T>::type) == 8) return __builtin_nontemporal_load(p);
     else return *p;
 }
 
 template <typename T>
 __device__ __forceinline__ void st_stream(T* p, T v)
 {
-    if constexpr (sizeof(T) == 8) __builtin_nontemporal_store(v, p);
+    if constexpr (sizeof(typename elem_of<T>::type) == 8) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
 
@@ -607,6 +612,39 @@ __device__ __forceinline__ void sweep_strided_reg(const DevPlan& P, const SweepA
     }
 }
 
+// The same for V adjacent lines per thread (V * sizeof(T) = 16 B): one vector load and store per
+// row for all V lines, which share the factor table (same j_V).  base and stride are multiples of V.
+template <typename T, int LM, int EPI, int V>
+__device__ __forceinline__ void sweep_strided_regv(const DevPlan& P, const SweepArgs& A, const Strided& L)
+{
+    typedef T vt __attribute__((ext_vector_type(V)));
+    constexpr int M = 1 << LM;
+    const T* in = (const T*)A.in;
+    const T* f = (const T*)P.fac + L.fac;
+    vt dp[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        const vt G = *(const vt*)(in + L.base + r * L.stride);
+        if (r == 0) dp[r] = G * f[0];
+        else dp[r] = G * f[r] - f[M + r] * dp[r - 1];
+    }
+    vt x = dp[M - 1];
+    auto put = [&](int64_t idx, vt v) {
+        if constexpr (EPI == EPI_STORE) {
+            *(vt*)((T*)A.out + idx) = v;         // (measured: plain faster than non-temporal here)
+        } else {
+            vt* W = (vt*)((T*)A.out + idx);
+            st_stream(W, ld_stream(W) + (T)A.b1 * ld_stream((const vt*)((const T*)A.K1 + idx)) + (T)A.b2 * v);
+        }
+    };
+    put(L.base + (int64_t)(M - 1) * L.stride, x);
+#pragma unroll
+    for (int r = M - 2; r >= 0; --r) {
+        x = dp[r] - f[2 * M + r] * x;
+        put(L.base + r * L.stride, x);
+    }
+}
+
 // Strided axis, long line: the forward sweep streams CHUNK rows at a time (loads batched) and leaves
 // d' in memory (the output, or the consumed input when updating); the backward sweep streams it back.
 template <typename T, int EPI>
@@ -646,31 +684,45 @@ __device__ __forceinline__ void sweep_strided_mem(const DevPlan& P, const SweepA
 }
 
 // Short strided lines (up to 2^SHORT_LM rows): one thread per line.
-template <typename T, int EPI>
+// Short strided lines (up to 2^SHORT_LM rows): one thread per V adjacent lines (V = 1, or
+// 16 B / sizeof(T) when the plan's units allow it on this axis).
+template <typename T, int EPI, int V>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
     const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
-    const int64_t gl = B.line_start + threadIdx.x;
+    const int64_t gl = B.line_start + (int64_t)threadIdx.x * V;
     if (gl >= B.line_end) return;
     const int64_t* lo = P.ax_line_off[axis];
     int k = B.k_start;
     while (gl >= lo[k + 1]) ++k;
     const UnitDev U = P.units[P.ax_units[axis][k]];
     const Strided L = strided_geom(P, U, axis, gl - lo[k], B.lm, A.run);
-    switch (B.lm) {
-    case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
-    case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
-    case 2: sweep_strided_reg<T, 2, EPI>(P, A, L); break;
-    case 3: sweep_strided_reg<T, 3, EPI>(P, A, L); break;
-    case 4: sweep_strided_reg<T, 4, EPI>(P, A, L); break;
-    default: break;   // longer classes go to k_sweep_strided_long
+    if constexpr (V == 1) {
+        switch (B.lm) {
+        case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
+        case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
+        case 2: sweep_strided_reg<T, 2, EPI>(P, A, L); break;
+        case 3: sweep_strided_reg<T, 3, EPI>(P, A, L); break;
+        case 4: sweep_strided_reg<T, 4, EPI>(P, A, L); break;
+        default: break;   // longer classes go to k_sweep_strided_long
+        }
+    } else {
+        switch (B.lm) {
+        case 0: sweep_strided_regv<T, 0, EPI, V>(P, A, L); break;
+        case 1: sweep_strided_regv<T, 1, EPI, V>(P, A, L); break;
+        case 2: sweep_strided_regv<T, 2, EPI, V>(P, A, L); break;
+        case 3: sweep_strided_regv<T, 3, EPI, V>(P, A, L); break;
+        case 4: sweep_strided_regv<T, 4, EPI, V>(P, A, L); break;
+        default: break;
+        }
     }
 }
 
 // Inclusive scan, in segment order (reversed when `rev`), of the affine maps c -> b + a c of the
-// segments of each line; returns the map of all segments before this one applied to 0, i.e. the
-// carry entering this segment.  sh: 4*SEG_BLOCK entries of LDS (two ping-pong buffers of (a, b),
-// segment-major), so each doubling round needs one barrier.
+// segments of each line slot (a slot is one line, or V adjacent lines as one vector T); returns the
+// map of all segments before this one applied to 0, i.e. the carry entering this segment.
+// sh: 4*SEG_BLOCK entries of LDS (two ping-pong buffers of (a, b), segment-major), so each
+// doubling round needs one barrier.
 template <typename T>
 __device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line, int lines, bool rev, T* sh)
 {
@@ -691,32 +743,50 @@ __device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line
         buf[SEG_BLOCK + at] = b;
         __syncthreads();
     }
-    const T cin = s > 0 ? buf[SEG_BLOCK + at - lines] : T(0);
+    const T cin = s > 0 ? buf[SEG_BLOCK + at - lines] : T{};
     __syncthreads();           // the buffers are reused by the next scan
     return cin;
 }
 
-// Long strided line split into nseg = M/S segments of S = sseg<T>() consecutive rows, one per thread,
-// kept in VGPRs.  Both Thomas recurrences are first order and linear, y_r = g_r inv_r - ainv_r
-// y_{r-1} and x_r = y_r - cp_r x_{r+1}: each thread runs them over its rows from a zero carry, the
-// segments' affine end maps are scanned in LDS to give every segment its true carry, and the rows
-// are corrected by the carry times the running product of the multipliers.  Every element is read
-// and written once, by the same thread (in-place safe).  All threads of the block must call it
+// Scalar or V-wide (ext_vector) element of the long-line solver.
+template <typename T, int V>
+struct lane_vec {
+    typedef T __attribute__((ext_vector_type(V))) type;
+};
+template <typename T>
+struct lane_vec<T, 1> {
+    typedef T type;
+};
+
+// Long strided line split into nseg = M/S segments of S = seg_rows consecutive rows, one per thread,
+// kept in VGPRs; with V > 1 the thread carries V adjacent lines (same factors) as one vector per
+// row.  Both Thomas recurrences are first order and linear, y_r = g_r inv_r - ainv_r y_{r-1} and
+// x_r = y_r - cp_r x_{r+1}: each thread runs them over its rows from a zero carry, the segments'
+// affine end maps are scanned in LDS to give every segment its true carry, and the rows are
+// corrected by the carry times the running product of the multipliers.  Every element is read and
+// written once, by the same thread (in-place safe).  All threads of the block must call it
 // (barriers); `live` is false for threads without a line.
-template <typename T, int EPI>
+template <typename T, int EPI, int V>
 __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepArgs& A, const Strided& L, int lm,
-                                                  bool live, int seg, int nseg, int line, int lines, T* sh)
+                                                  bool live, int seg, int nseg, int line, int lines,
+                                                  typename lane_vec<T, V>::type* sh)
 {
+    typedef typename lane_vec<T, V>::type vt;
     const int M = 1 << lm;
-    constexpr int SSEG = sseg<T>();
+    constexpr int SSEG = seg_rows((int)sizeof(T), V);
     const int r0 = seg * SSEG;
     const T* f = (const T*)P.fac + (live ? L.fac : 0);
-    T v[SSEG];
-    T y = T(0), mu = T(1);
+    const vt one = vt{} + T(1);
+    vt v[SSEG];
+    vt y{}, mu = one;
     if (live) {
         const T* in = (const T*)A.in;
 #pragma unroll
-        for (int k = 0; k < SSEG; ++k) v[k] = ld_stream(in + L.base + (int64_t)(r0 + k) * L.stride);
+        for (int k = 0; k < SSEG; ++k) {
+            const T* src = in + L.base + (int64_t)(r0 + k) * L.stride;
+            if constexpr (V == 1) v[k] = ld_stream(src);
+            else v[k] = *(const vt*)src;
+        }
 #pragma unroll
         for (int k = 0; k < SSEG; ++k) {
             const T ai = f[M + r0 + k];
@@ -725,8 +795,8 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
             v[k] = y;
         }
     }
-    const T yin = segment_carry<T>(mu, y, seg, nseg, line, lines, false, sh);
-    T x = T(0), nu = T(1);
+    const vt yin = segment_carry<vt>(mu, y, seg, nseg, line, lines, false, sh);
+    vt x{}, nu = one;
     if (live) {
         T m = T(1);
 #pragma unroll
@@ -742,7 +812,7 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
             v[k] = x;
         }
     }
-    const T xin = segment_carry<T>(nu, x, seg, nseg, line, lines, true, sh);
+    const vt xin = segment_carry<vt>(nu, x, seg, nseg, line, lines, true, sh);
     if (live) {
         T n = T(1);
 #pragma unroll
@@ -751,22 +821,33 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
             v[k] = v[k] + n * xin;
         }
 #pragma unroll
-        for (int k = 0; k < SSEG; ++k) sweep_store<T, EPI>(A, L.base + (int64_t)(r0 + k) * L.stride, v[k]);
+        for (int k = 0; k < SSEG; ++k) {
+            const int64_t idx = L.base + (int64_t)(r0 + k) * L.stride;
+            if constexpr (V == 1) {
+                sweep_store<T, EPI>(A, idx, v[k]);
+            } else if constexpr (EPI == EPI_STORE) {
+                *(vt*)((T*)A.out + idx) = v[k];
+            } else {
+                vt* W = (vt*)((T*)A.out + idx);
+                st_stream(W, ld_stream(W) + (T)A.b1 * ld_stream((const vt*)((const T*)A.K1 + idx)) + (T)A.b2 * v[k]);
+            }
+        }
     }
 }
 
-// Strided lines longer than 2^SHORT_LM rows.  Classes up to SEG_BLOCK*sseg rows: SEG_BLOCK*sseg/M
-// lines per block, thread t on line t mod lines and segment t / lines (lanes on consecutive lines,
-// coalesced); longer lines: one thread per line through memory.
-template <typename T, int EPI>
+// Strided lines longer than 2^SHORT_LM rows.  Classes up to SEG_BLOCK*seg_rows rows: SEG_BLOCK*seg_rows/M
+// line slots of V adjacent lines per block, thread t on slot t mod slots and segment t / slots
+// (lanes on consecutive slots, coalesced); longer lines: one thread per line through memory.
+template <typename T, int EPI, int V>
 __global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
-    __shared__ T sh[4 * SEG_BLOCK];
+    typedef typename lane_vec<T, V>::type vt;
+    __shared__ vt sh[4 * SEG_BLOCK];
     const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
     const int lm = B.lm;
     const int64_t* lo = P.ax_line_off[axis];
-    constexpr int SSEG = sseg<T>();
-    if (lm > seg_max_lm((int)sizeof(T))) {      // block-uniform branch
+    constexpr int SSEG = seg_rows((int)sizeof(T), V);
+    if (lm > seg_max_lm((int)sizeof(T), V)) {   // block-uniform branch
         const int64_t gl = B.line_start + threadIdx.x;
         if (gl >= B.line_end) return;
         int k = B.k_start;
@@ -775,10 +856,10 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, Swe
         sweep_strided_mem<T, EPI>(P, A, strided_geom(P, U, axis, gl - lo[k], lm, A.run), lm);
         return;
     }
-    const int lines = (SEG_BLOCK * SSEG) >> lm;
-    const int line = threadIdx.x & (lines - 1);
-    const int seg = threadIdx.x >> (__ffs(lines) - 1);
-    const int64_t gl = B.line_start + line;
+    const int slots = (SEG_BLOCK * SSEG) >> lm;
+    const int slot = threadIdx.x & (slots - 1);
+    const int seg = threadIdx.x >> (__ffs(slots) - 1);
+    const int64_t gl = B.line_start + (int64_t)slot * V;
     const bool live = gl < B.line_end;
     Strided L{};
     if (live) {
@@ -787,7 +868,7 @@ __global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, Swe
         const UnitDev& U = P.units[P.ax_units[axis][k]];
         L = strided_geom(P, U, axis, gl - lo[k], lm, A.run);
     }
-    sweep_strided_seg<T, EPI>(P, A, L, lm, live, seg, (1 << lm) / SSEG, line, lines, sh);
+    sweep_strided_seg<T, EPI, V>(P, A, L, lm, live, seg, (1 << lm) / SSEG, slot, slots, sh);
 }
 
 // Axis 0 (contiguous lines).  Coefficients are formed on the fly: delta_r = tdiff_0[r] * V^2.
@@ -1357,10 +1438,28 @@ static void sweep_part(const DevPlan& P, int axis, int epi, const SweepArgs& a, 
 {
     dim3 g((unsigned)nb), b(LINE_BLOCK), bl(SEG_BLOCK);
     if (axis == 0) hipLaunchKernelGGL((k_sweep_contig<T, LONG>), g, b, 0, s, P, a, b0);
-    else if (!LONG && epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE>), g, b, 0, s, P, a, axis, b0);
-    else if (!LONG) hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE>), g, b, 0, s, P, a, axis, b0);
-    else if (epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_STORE>), g, bl, 0, s, P, a, axis, b0);
-    else hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_UPDATE>), g, bl, 0, s, P, a, axis, b0);
+    else if (!LONG) {
+        constexpr int VW = 16 / (int)sizeof(T);
+        const bool vec = P.ax_vec[axis] > 1;
+        if (epi == EPI_STORE) {
+            if (vec) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE, VW>), g, b, 0, s, P, a, axis, b0);
+            else hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE, 1>), g, b, 0, s, P, a, axis, b0);
+        } else {
+            if (vec) hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE, VW>), g, b, 0, s, P, a, axis, b0);
+            else hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE, 1>), g, b, 0, s, P, a, axis, b0);
+        }
+    }
+    else {
+        constexpr int VW = 16 / (int)sizeof(T);
+        const bool vec = P.ax_vec[axis] > 1;
+        if (epi == EPI_STORE) {
+            if (vec) hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_STORE, VW>), g, bl, 0, s, P, a, axis, b0);
+            else hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_STORE, 1>), g, bl, 0, s, P, a, axis, b0);
+        } else {
+            if (vec) hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_UPDATE, VW>), g, bl, 0, s, P, a, axis, b0);
+            else hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_UPDATE, 1>), g, bl, 0, s, P, a, axis, b0);
+        }
+    }
 }
 
 hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part, const SweepArgs& a,
