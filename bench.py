@@ -36,7 +36,7 @@ def kernel_class_of(name: str):
     from paper_2408_00559_amd import _lib as L
     for sym, lg in (("k_sweep_strided_long<", True), ("k_sweep_strided<", False)):
         if sym in name:
-            args = [a.strip() for a in name.split(sym, 1)[1].split(">", 1)[0].split(",")]   # <T, EPI, V>
+            args = [a.strip() for a in name.split(sym, 1)[1].split(">", 1)[0].split(",")]   # <T, EPI[, V]>
             up = args[1] in ("1", "EPI_UPDATE", "amf::EPI_UPDATE")
             return ("sweep_update" if up else "sweep_strided") + ("_long" if lg else "")
     if "k_sweep_contig<" in name:

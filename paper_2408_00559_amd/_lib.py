@@ -64,9 +64,9 @@ K_NAMES = ["init", "operator", "stage1", "stage2", "refine", "sweep_contig", "sw
 K_SYMBOLS = {"init": "k_node", "operator": "k_stencil<OP_F_PAYOFF>", "stage1": "k_stencil_vec<OP_STAGE1, R, FUSE>",
              "stage2": "k_stencil_vec<OP_STAGE2, R, FUSE>", "refine": "k_stencil_vec<OP_REFINE, R, FUSE>",
              "sweep_contig": "k_sweep_contig<false>", "sweep_contig_long": "k_sweep_contig<true>",
-             "sweep_strided": "k_sweep_strided<EPI_STORE, V>",
+             "sweep_strided": "k_sweep_strided<EPI_STORE>",
              "sweep_strided_long": "k_sweep_strided_long<EPI_STORE, V>",
-             "sweep_update": "k_sweep_strided<EPI_UPDATE, V>",
+             "sweep_update": "k_sweep_strided<EPI_UPDATE>",
              "sweep_update_long": "k_sweep_strided_long<EPI_UPDATE, V>",
              "unit_values": "k_unit_values", "combine": "k_combine", "resident": "k_resident"}
 K_COUNT = len(K_NAMES)

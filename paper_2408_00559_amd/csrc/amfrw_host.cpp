@@ -470,25 +470,53 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             for (int u = 0; u < P->n_units; ++u)
                 if (P->units[u].lv[ax] <= SHORT_LM) short_pts += (int64_t)1 << P->units[u].lsum;
             P->ax_short_frac[ax] = P->inner > 0 ? (double)short_pts / (double)P->inner : 0.0;
-            // strided lines: a thread (short lines) or a segment slot (long lines) takes V = 16 B / elem
-            // adjacent lines, one vector per row, when every unit has runs of at least V adjacent
-            // lines on this axis
-            int vec = ax > 0 ? 16 / (int)P->elem : 1;
-            for (int u = 0; u < P->n_units && vec > 1; ++u) {
+            // strided lines: V = 16 B / elem adjacent lines carried as one vector per row.  Short
+            // lines: per block, when each of its units has runs of at least V adjacent lines on
+            // this axis (E = 2^(levels below the axis) >= V); long lines: when every unit has.
+            const int vw = ax > 0 ? 16 / (int)P->elem : 1;
+            auto unit_vec_ok = [&](int u) {
                 int S = 0;
                 for (int i = 0; i < ax; ++i) S += P->units[u].lv[i];
-                if ((1 << S) < vec) vec = 1;
-            }
+                return vw > 1 && (1 << S) >= vw;
+            };
+            int vec = vw;
+            for (int u = 0; u < P->n_units && vec > 1; ++u)
+                if (!unit_vec_ok(u)) vec = 1;
             P->ax_vec[ax] = vec;
             int k0 = 0;
             while (k0 < P->n_units) {
                 const int lm = P->units[ord[k0]].lv[ax];
                 int k1 = k0;
                 while (k1 < P->n_units && P->units[ord[k1]].lv[ax] == lm) ++k1;
+                if (ax > 0 && lm <= SHORT_LM) {
+                    // runs of units with the same vector eligibility, blocks of LINE_BLOCK threads
+                    int ka = k0;
+                    while (ka < k1) {
+                        const bool ok = unit_vec_ok(ord[ka]);
+                        int kb = ka;
+                        while (kb < k1 && unit_vec_ok(ord[kb]) == ok) ++kb;
+                        const int v = ok ? vw : 1;
+                        const int per = LINE_BLOCK * v;
+                        int k = ka;
+                        for (int64_t s = lo[ka]; s < lo[kb]; s += per) {
+                            while (s >= lo[k + 1]) ++k;
+                            SweepBlk B{};
+                            B.line_start = s;
+                            B.line_end = std::min<int64_t>(s + per, lo[kb]);
+                            B.k_start = k;
+                            B.lm = lm;
+                            B.vec = v;
+                            P->ax_blk[ax].push_back(B);
+                        }
+                        ka = kb;
+                    }
+                    k0 = k1;
+                    continue;
+                }
                 int k = k0;
                 // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each
                 // longer strided lines: M/seg_rows threads per line slot in blocks of SEG_BLOCK threads
-                int per = LINE_BLOCK * (ax > 0 && lm <= SHORT_LM ? vec : 1);
+                int per = LINE_BLOCK;
                 const int ss = seg_rows((int)P->elem, vec);
                 if (ax == 0 && lm > CONTIG_REG_LM) per = LINE_BLOCK / ((1 << lm) / SEG);
                 else if (ax > 0 && lm > SHORT_LM)
@@ -500,6 +528,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                     B.line_end = std::min<int64_t>(s + per, lo[k1]);
                     B.k_start = k;
                     B.lm = lm;
+                    B.vec = ax > 0 ? vec : 1;
                     P->ax_blk[ax].push_back(B);
                 }
                 k0 = k1;

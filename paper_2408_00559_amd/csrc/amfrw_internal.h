@@ -76,12 +76,15 @@ struct alignas(16) ProbDev {
 };
 
 // A block of the sweep along one axis: lines [line_start, line_end) of the axis' line list, all
-// of length 2^lm; k_start indexes the axis' unit list at line_start.
+// of length 2^lm; k_start indexes the axis' unit list at line_start; vec: adjacent lines per
+// thread of the short-line sweep (1, or 16 B / element when all the block's units allow it).
 struct alignas(16) SweepBlk {
     int64_t line_start;
     int64_t line_end;
     int32_t k_start;
     int32_t lm;
+    int32_t vec;
+    int32_t pad_;
 };
 
 // Device view of a bound plan (pointers into the workspace).
@@ -106,7 +109,7 @@ struct DevPlan {
     const SweepBlk* ax_blk[MAXD];
     int64_t ax_nblk[MAXD];
     int64_t ax_nblk_short[MAXD];       // leading blocks with lm <= SHORT_LM
-    int ax_vec[MAXD];                  // short strided lines: 16-byte vectors of adjacent lines per thread
+    int ax_vec[MAXD];                  // long strided lines: 16-byte vectors of adjacent lines per slot
 };
 
 // Stencil operation selector.  Solution vectors are stored as W = Y - g (zero on every lower face);

@@ -684,20 +684,21 @@ __device__ __forceinline__ void sweep_strided_mem(const DevPlan& P, const SweepA
 }
 
 // Short strided lines (up to 2^SHORT_LM rows): one thread per line.
-// Short strided lines (up to 2^SHORT_LM rows): one thread per V adjacent lines (V = 1, or
-// 16 B / sizeof(T) when the plan's units allow it on this axis).
-template <typename T, int EPI, int V>
+// Short strided lines (up to 2^SHORT_LM rows): one thread per B.vec adjacent lines (1, or
+// VW = 16 B / sizeof(T) when all the block's units allow it: one vector load and store per row).
+template <typename T, int EPI>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
+    constexpr int VW = 16 / (int)sizeof(T);
     const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
-    const int64_t gl = B.line_start + (int64_t)threadIdx.x * V;
+    const int64_t gl = B.line_start + (int64_t)threadIdx.x * B.vec;
     if (gl >= B.line_end) return;
     const int64_t* lo = P.ax_line_off[axis];
     int k = B.k_start;
     while (gl >= lo[k + 1]) ++k;
     const UnitDev U = P.units[P.ax_units[axis][k]];
     const Strided L = strided_geom(P, U, axis, gl - lo[k], B.lm, A.run);
-    if constexpr (V == 1) {
+    if (B.vec == 1) {                           // block-uniform
         switch (B.lm) {
         case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
         case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
@@ -708,11 +709,11 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepAr
         }
     } else {
         switch (B.lm) {
-        case 0: sweep_strided_regv<T, 0, EPI, V>(P, A, L); break;
-        case 1: sweep_strided_regv<T, 1, EPI, V>(P, A, L); break;
-        case 2: sweep_strided_regv<T, 2, EPI, V>(P, A, L); break;
-        case 3: sweep_strided_regv<T, 3, EPI, V>(P, A, L); break;
-        case 4: sweep_strided_regv<T, 4, EPI, V>(P, A, L); break;
+        case 0: sweep_strided_regv<T, 0, EPI, VW>(P, A, L); break;
+        case 1: sweep_strided_regv<T, 1, EPI, VW>(P, A, L); break;
+        case 2: sweep_strided_regv<T, 2, EPI, VW>(P, A, L); break;
+        case 3: sweep_strided_regv<T, 3, EPI, VW>(P, A, L); break;
+        case 4: sweep_strided_regv<T, 4, EPI, VW>(P, A, L); break;
         default: break;
         }
     }
@@ -1438,17 +1439,8 @@ static void sweep_part(const DevPlan& P, int axis, int epi, const SweepArgs& a, 
 {
     dim3 g((unsigned)nb), b(LINE_BLOCK), bl(SEG_BLOCK);
     if (axis == 0) hipLaunchKernelGGL((k_sweep_contig<T, LONG>), g, b, 0, s, P, a, b0);
-    else if (!LONG) {
-        constexpr int VW = 16 / (int)sizeof(T);
-        const bool vec = P.ax_vec[axis] > 1;
-        if (epi == EPI_STORE) {
-            if (vec) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE, VW>), g, b, 0, s, P, a, axis, b0);
-            else hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE, 1>), g, b, 0, s, P, a, axis, b0);
-        } else {
-            if (vec) hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE, VW>), g, b, 0, s, P, a, axis, b0);
-            else hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE, 1>), g, b, 0, s, P, a, axis, b0);
-        }
-    }
+    else if (!LONG && epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE>), g, b, 0, s, P, a, axis, b0);
+    else if (!LONG) hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE>), g, b, 0, s, P, a, axis, b0);
     else {
         constexpr int VW = 16 / (int)sizeof(T);
         const bool vec = P.ax_vec[axis] > 1;
