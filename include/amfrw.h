@@ -189,7 +189,7 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
 /* Launch schedule of a plan (tuning knobs; results do not depend on them beyond rounding order
  * of independent per-node sums, which they leave unchanged).
  *   stencil_nodes: consecutive axis-1 nodes evaluated per thread by the time-loop operator
- *                  (1, 2 or 4; at most max_stencil_nodes = min(4, smallest M_1 of the plan)).
+ *                  (1, 2, 4 or 8; at most max_stencil_nodes = min(8, smallest M_1 of the plan)).
  *   xcd_remap:     assign each XCD a contiguous share of the blocks, so that blocks reading the
  *                  same halo planes share that XCD's L2: 1 = operator launches only, 2 = every
  *                  streaming launch (operators, sweeps, per-node kernels), 0 = off.

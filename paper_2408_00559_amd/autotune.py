@@ -27,7 +27,7 @@ def signature(plan) -> str:
 
 def candidates(plan):
     sc = plan.schedule()
-    nodes = [r for r in (1, 2, 4) if r <= sc["max_stencil_nodes"]]
+    nodes = [r for r in (1, 2, 4, 8) if r <= sc["max_stencil_nodes"]]
     out = [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=0)
            for r, x in itertools.product(nodes, (0, 1, 2))]
     out += [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=1)

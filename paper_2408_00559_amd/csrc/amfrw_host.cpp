@@ -47,7 +47,7 @@ struct amf_plan {
     int64_t fac_run = 0;                   // elements per run in facd
     std::vector<ProbDev> probdev;
     std::vector<int32_t> blk_unit;
-    std::vector<int32_t> blk_unit_r[3];    // node blocks of NODE_BLOCK * {1, 2, 4} nodes
+    std::vector<int32_t> blk_unit_r[4];    // node blocks of NODE_BLOCK * {1, 2, 4, 8} nodes
     int stencil_r = 1, min_m0 = 1, max_m0 = 1, xcd = 1;
     int fuse0 = 0;                         // fused axis-0 solve in the operator launches
     bool res_ok = false;                   // every unit fits the unit-resident schedule
@@ -61,7 +61,7 @@ struct amf_plan {
     int64_t inner = 0;                     // inner points over all units
 
     size_t off_vec[N_VEC]{}, off_units = 0, off_probs = 0, off_tab = 0, off_fac = 0, off_blk = 0;
-    size_t off_blkr[3]{};
+    size_t off_blkr[4]{};
     size_t off_axu[MAXD]{}, off_axl[MAXD]{}, off_axb[MAXD]{};
     size_t off_coef = 0, off_vals = 0, off_valsc = 0, ws_bytes = 0;
     size_t elem = 8;
@@ -436,7 +436,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             }
         };
         block_table(NODE_BLOCK, P->blk_unit);
-        for (int k = 0; k < 3; ++k) block_table((int64_t)NODE_BLOCK << k, P->blk_unit_r[k]);
+        for (int k = 0; k < 4; ++k) block_table((int64_t)NODE_BLOCK << k, P->blk_unit_r[k]);
         // time-loop operator: R consecutive axis-0 nodes per thread, R <= every unit's M_0
         int min_m0 = 1 << 16, max_m0 = 1;
         for (int u = 0; u < P->n_units; ++u) {
@@ -552,7 +552,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->off_tab = take(P->tabd.size() * P->elem);
         P->off_fac = take(P->facd.size() * P->elem);
         P->off_blk = take(P->blk_unit.size() * sizeof(int32_t));
-        for (int k = 0; k < 3; ++k) P->off_blkr[k] = take(P->blk_unit_r[k].size() * sizeof(int32_t));
+        for (int k = 0; k < 4; ++k) P->off_blkr[k] = take(P->blk_unit_r[k].size() * sizeof(int32_t));
         for (int ax = 0; ax < d; ++ax) {
             P->off_axu[ax] = take(P->ax_units[ax].size() * sizeof(int32_t));
             P->off_axl[ax] = take(P->ax_line_off[ax].size() * sizeof(int64_t));
@@ -631,7 +631,7 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
         if ((st = upload(P->ws + P->off_fac, ff.data(), ff.size() * 4, s))) return st;
     }
     if ((st = upload(P->ws + P->off_blk, P->blk_unit.data(), P->blk_unit.size() * 4, s))) return st;
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 4; ++k)
         if ((st = upload(P->ws + P->off_blkr[k], P->blk_unit_r[k].data(), P->blk_unit_r[k].size() * 4, s))) return st;
     for (int ax = 0; ax < P->d; ++ax) {
         if ((st = upload(P->ws + P->off_axu[ax], P->ax_units[ax].data(), P->ax_units[ax].size() * 4, s))) return st;
@@ -657,7 +657,7 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
     D.n_node_blocks = (int64_t)P->blk_unit.size();
     D.stencil_r = P->stencil_r;
     D.xcd = P->xcd;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
         D.blk_unit_r[k] = (const int32_t*)(P->ws + P->off_blkr[k]);
         D.n_blocks_r[k] = (int64_t)P->blk_unit_r[k].size();
     }
@@ -1040,7 +1040,7 @@ amf_status amf_schedule_get(const amf_plan* P, amf_schedule* out)
     out->struct_size = sizeof(amf_schedule);
     out->stencil_nodes = P->stencil_r;
     out->xcd_remap = P->xcd;
-    out->max_stencil_nodes = std::min(4, P->min_m0);
+    out->max_stencil_nodes = std::min(8, P->min_m0);
     out->resident = P->resident;
     out->resident_available = P->res_ok ? 1 : 0;
     out->fuse_axis0 = P->fuse0;
@@ -1052,7 +1052,7 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
 {
     if (!P || !sc || sc->struct_size != sizeof(amf_schedule)) return fail(AMF_E_INVALID, "bad amf_schedule");
     const int r = sc->stencil_nodes;
-    if (r != 1 && r != 2 && r != 4) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2 or 4");
+    if (r != 1 && r != 2 && r != 4 && r != 8) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2, 4 or 8");
     if (r > P->min_m0) return fail(AMF_E_INVALID, "stencil_nodes exceeds the smallest axis-1 line");
     if (sc->xcd_remap < 0 || sc->xcd_remap > 2) return fail(AMF_E_INVALID, "xcd_remap must be 0, 1 or 2");
     if (sc->resident != 0 && sc->resident != 1) return fail(AMF_E_INVALID, "resident must be 0 or 1");

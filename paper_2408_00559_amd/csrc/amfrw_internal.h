@@ -32,6 +32,8 @@ constexpr int seg_max_lm(int elem, int vec)
 }
 constexpr int CHUNK = 4;
 constexpr int NXCD = 8;
+// index of the node-block table for R nodes per thread (R = 1, 2, 4, 8)
+constexpr int r_index(int R) { return R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0; }
 // Default nodes per thread of the time-loop operator, by precision (limited by each unit's M_0);
 // a plan's schedule may override it.
 constexpr int STENCIL_R_F64 = 4;
@@ -100,10 +102,10 @@ struct DevPlan {
     int64_t fac_run_stride;      // elements between the run-0 and run-1 factor tables
     const int32_t* blk_unit;     // per node block: first unit
     int64_t n_node_blocks;
-    int stencil_r;               // nodes per thread of the time-loop operator (1, 2 or 4)
+    int stencil_r;               // nodes per thread of the time-loop operator (1, 2, 4 or 8)
     int xcd;                     // 1: XCD-aware block remapping
-    const int32_t* blk_unit_r[3];   // per block of NODE_BLOCK * R nodes (R = 1, 2, 4): first unit
-    int64_t n_blocks_r[3];
+    const int32_t* blk_unit_r[4];   // per block of NODE_BLOCK * R nodes (R = 1, 2, 4, 8): first unit
+    int64_t n_blocks_r[4];
     const int32_t* ax_units[MAXD];     // per axis: units ordered by M_axis
     const int64_t* ax_line_off[MAXD];  // per axis: first line of each listed unit (+ sentinel)
     const SweepBlk* ax_blk[MAXD];

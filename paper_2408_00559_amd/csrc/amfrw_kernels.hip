@@ -342,7 +342,7 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
     int u = 0;
     int64_t loc = 0;
     if (live) {
-        u = find_unit(P.units, P.blk_unit_r[R == 4 ? 2 : 1][lb], g);
+        u = find_unit(P.units, P.blk_unit_r[r_index(R)][lb], g);
         loc = g - P.units[u].off;
         live = loc < ((int64_t)1 << P.units[u].lsum);     // else alignment padding
     }
@@ -1375,7 +1375,7 @@ hipError_t launch_state_read(const DevPlan& P, int prec, const void* W, void* Y,
 template <typename T, int D, int R>
 static hipError_t stencil_vec(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
-    dim3 g((unsigned)P.n_blocks_r[R == 4 ? 2 : 1]), b(NODE_BLOCK);
+    dim3 g((unsigned)P.n_blocks_r[r_index(R)]), b(NODE_BLOCK);
     const bool fuse = a.S != nullptr;
     switch (op) {
     case OP_STAGE1:
@@ -1399,6 +1399,7 @@ template <typename T, int D>
 static hipError_t stencil_td(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
     const bool hot = op == OP_STAGE1 || op == OP_STAGE2 || op == OP_REFINE;
+    if (hot && P.stencil_r == 8) return stencil_vec<T, D, 8>(P, op, a, s);
     if (hot && P.stencil_r == 4) return stencil_vec<T, D, 4>(P, op, a, s);
     if (hot && P.stencil_r == 2) return stencil_vec<T, D, 2>(P, op, a, s);
     if (a.S != nullptr) return hipErrorInvalidValue;     // the fused form needs 2 or 4 nodes per thread

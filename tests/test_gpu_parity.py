@@ -241,7 +241,7 @@ def test_schedules_agree(name):
         return oracle.inner_view(Yf, lv)
 
     refs = parallel(ref, items)
-    for r in (1, 2, 4):
+    for r in (1, 2, 4, 8):
         if r > mx:
             continue
         for x in (0, 1, 2):
@@ -347,7 +347,7 @@ def test_fused_axis0_schedule(name, precision, tol):
     probs, grid = CASES[name]
     steps = 5
     plan = Plan(probs, grid, steps=steps, precision=precision, device=DEV)
-    rs = [r for r in (4, 2) if r <= plan.schedule()["max_stencil_nodes"] and plan.fuse_allowed(r)]
+    rs = [r for r in (8, 4, 2) if r <= plan.schedule()["max_stencil_nodes"] and plan.fuse_allowed(r)]
     if not rs:
         pytest.skip("no operator width admits the fused axis-0 solve")
     items = unit_slices(plan)
