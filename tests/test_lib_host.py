@@ -137,3 +137,70 @@ def test_state_calls_need_bound_workspace():
     assert L.lib().amf_time_step(h, 1, None) == L.E_STATE
     L.lib().amf_plan_destroy(h)
     L.lib().amf_plan_destroy(None)
+
+
+def _sched(h):
+    sc = L.AmfSchedule()
+    sc.struct_size = C.sizeof(L.AmfSchedule)
+    L.check(L.lib().amf_schedule_get(h, C.byref(sc)))
+    return sc
+
+
+def _set(h, **kw):
+    sc = _sched(h)
+    for k, v in kw.items():
+        setattr(sc, k, v)
+    return L.lib().amf_schedule_set(h, C.byref(sc))
+
+
+def test_schedule_validation():
+    """Launch knobs are checked on the host: node counts, XCD modes, the fused axis-0 solve's
+    block-size condition (256 * stencil_nodes >= the longest axis-0 line) and the resident limit."""
+    w = I.workload_ct4()
+    st, h = _create(w["problems"], w["grid"], steps=w["steps"])
+    assert st == L.OK
+    sc = _sched(h)
+    assert (sc.max_stencil_nodes, sc.fuse_max_axis0, sc.resident_available) == (8, 1024, 0)
+    assert _set(h, stencil_nodes=3) == L.E_INVALID
+    assert _set(h, stencil_nodes=16) == L.E_INVALID
+    assert _set(h, xcd_remap=3) == L.E_INVALID
+    assert _set(h, resident=1) == L.E_INVALID               # grids of 2^16..2^19 points
+    assert _set(h, stencil_nodes=2, fuse_axis0=1) == L.E_INVALID   # 512 < 1024-node lines
+    assert _set(h, stencil_nodes=4, fuse_axis0=1) == L.OK
+    assert _set(h, stencil_nodes=8, fuse_axis0=1, xcd_remap=2) == L.OK
+    assert _sched(h).fuse_axis0 == 1
+    assert _set(h, stencil_nodes=1, fuse_axis0=1) == L.E_INVALID
+    L.lib().amf_plan_destroy(h)
+    # a plan whose smallest axis-0 line has 2 nodes allows at most 2 nodes per thread
+    p = I.draw_instances(1, seed=9, d=3)[0]
+    st, h = _create([p], I.combination(4, 1))
+    sc = _sched(h)
+    assert sc.max_stencil_nodes == 2 and sc.resident_available == 1
+    assert _set(h, stencil_nodes=4) == L.E_INVALID
+    assert _set(h, resident=1) == L.OK
+    L.lib().amf_plan_destroy(h)
+
+
+@pytest.mark.parametrize("d,n,psi,count", [(4, 7, 3, 1), (4, 6, 1, 3), (3, 5, 0, 2), (6, 5, 1, 1)])
+def test_unit_offsets_keep_axis0_lines_inside_operator_blocks(d, n, psi, count):
+    """Unit offsets are multiples of 64 elements and of min(M_0, 1024), and units do not overlap:
+    a node block of 256 R >= M_0 nodes then never splits an axis-0 line (the fused axis-0 solve
+    relies on it)."""
+    probs = I.draw_instances(count, seed=3, d=d)
+    st, h = _create(probs, I.combination(n, psi))
+    assert st == L.OK
+    info = L.AmfPlanInfo()
+    L.check(L.lib().amf_plan_info_get(h, C.byref(info)))
+    prob = C.c_int32()
+    lv = (C.c_int32 * L.MAX_D)()
+    cf = C.c_double()
+    off = C.c_int64()
+    end = 0
+    for u in range(info.n_units):
+        L.check(L.lib().amf_unit_info(h, u, C.byref(prob), lv, C.byref(cf), C.byref(off)))
+        m0 = 1 << lv[0]
+        assert off.value % 64 == 0 and off.value % min(m0, 1024) == 0, (u, off.value, m0)
+        assert off.value >= end
+        end = off.value + (1 << sum(lv[i] for i in range(d)))
+    assert end * (8 if info.precision == L.FP64 else 4) <= info.vector_bytes
+    L.lib().amf_plan_destroy(h)
