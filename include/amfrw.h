@@ -103,7 +103,8 @@ typedef struct {
     uint64_t workspace_bytes;
     uint64_t state_offset;            /* byte offset of the stored Y - g inside the workspace      */
     uint64_t vector_bytes;            /* bytes of one grid vector: all units, each unit's offset   */
-                                      /* rounded up to 64 elements (padding is never read)         */
+                                      /* rounded up to a multiple of 64 elements and of             */
+                                      /* min(M_1, 1024) (padding is never read)                     */
     int32_t d;
     int32_t precision;                /* amf_precision                                             */
     int32_t n_steps;
@@ -186,8 +187,9 @@ amf_status amf_apply_operator(amf_plan* plan, const void* d_in, void* d_out, int
                               double scale, void* stream);
 amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* d_out, void* stream);
 
-/* Launch schedule of a plan (tuning knobs; results do not depend on them beyond rounding order
- * of independent per-node sums, which they leave unchanged).
+/* Launch schedule of a plan (tuning knobs).  Results agree across schedules up to rounding: the
+ * operator's per-node arithmetic is the same in every schedule, but the fused axis-1 solve and the
+ * unit-resident schedule order the tridiagonal recurrences differently from the streaming sweeps.
  *   stencil_nodes: consecutive axis-1 nodes evaluated per thread by the time-loop operator
  *                  (1, 2, 4 or 8; at most max_stencil_nodes = min(8, smallest M_1 of the plan)).
  *   xcd_remap:     assign each XCD a contiguous share of the blocks, so that blocks reading the

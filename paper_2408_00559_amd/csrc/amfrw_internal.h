@@ -11,8 +11,6 @@ constexpr int NODE_BLOCK = 256;    // threads per block of the per-node kernels
 constexpr int LINE_BLOCK = 256;    // threads per block of the sweep kernels
 constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
-// Longest strided line kept whole in VGPRs by one thread (log2) in the short-line launch.
-constexpr int REG_LM = 5;
 // Longer strided lines: seg_rows consecutive rows per thread (one line: 8 in FP64, 32 in FP32;
 // measured on the d = 4 workload), M/seg_rows threads per line, blocks of SEG_BLOCK threads
 // (SEG_BLOCK*seg_rows/M line slots each), up to SEG_BLOCK*seg_rows rows; beyond that one thread
@@ -31,13 +29,13 @@ constexpr int seg_max_lm(int elem, int vec)
     return l;
 }
 constexpr int CHUNK = 4;
-constexpr int NXCD = 8;
+constexpr int NXCD = 8;            // MI355X: 8 XCDs, each with its own L2
 // index of the node-block table for R nodes per thread (R = 1, 2, 4, 8)
 constexpr int r_index(int R) { return R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0; }
 // Default nodes per thread of the time-loop operator, by precision (limited by each unit's M_0);
-// a plan's schedule may override it.
+// a plan's schedule may override it (the autotuner picks among 1, 2, 4, 8).
 constexpr int STENCIL_R_F64 = 4;
-constexpr int STENCIL_R_F32 = 4;            // MI355X: 8 XCDs, each with its own L2
+constexpr int STENCIL_R_F32 = 4;
 // Contiguous (axis 0) lines up to 2^CONTIG_REG_LM are solved by one thread; longer ones by SEG-row
 // segments on M/SEG cooperating lanes.
 constexpr int CONTIG_REG_LM = 4;
