@@ -300,9 +300,12 @@ def run_surrogate(torch, Plan):
     return res
 
 
-def cpu_baseline(w, max_seconds_hint=20.0):
+def cpu_baseline(w, target_seconds=12.0):
     """The FP64 oracle on a bounded sample of the same workload: the smallest combination layer
-    (35 component grids of 65,536 inner points) for a few of the 100 time steps, all host cores."""
+    (35 component grids of 65,536 inner points) for as many of the 100 time steps, at the workload's
+    dt, as take about `target_seconds` on all host cores (a 6-step run sizes it)."""
+    import ctypes as C
+
     import numpy as np
 
     import oracle
@@ -311,26 +314,30 @@ def cpu_baseline(w, max_seconds_hint=20.0):
     lv, cf = oracle.ct_grids(p.d, w["grid"].n, w["grid"].psi)
     sums = lv.sum(axis=1)
     sel = lv[sums == sums.min()]
-    steps = 6
     threads = oracle.max_threads()
     sc = oracle.scheme_amfrw2()
-    ps = oracle.problem_struct(p)
-    import ctypes as C
     L = oracle.lib()
     lvc = np.ascontiguousarray(sel, dtype=np.int32)
     coef = np.ones(len(sel))
     units = np.empty(len(sel))
     out = np.zeros(1)
-    # dt of the workload (T / 100 steps) and `steps` of them: orc_price_grids solves to T with the
-    # given step count, so scale the maturity to keep dt unchanged.
-    ps.T = p.T * steps / w["steps"]
-    t0 = time.perf_counter()
-    rc = L.orc_price_grids(C.byref(ps), lvc.ctypes.data_as(C.POINTER(C.c_int32)),
-                           coef.ctypes.data_as(C.POINTER(C.c_double)), len(sel), C.byref(sc), steps,
-                           threads, units.ctypes.data_as(C.POINTER(C.c_double)),
-                           out.ctypes.data_as(C.POINTER(C.c_double)))
-    dt = time.perf_counter() - t0
-    assert rc == 0
+
+    def run(steps):
+        # orc_price_grids solves to the problem's maturity with `steps` steps: scale the maturity
+        # so that dt stays the workload's T / steps
+        ps = oracle.problem_struct(p)
+        ps.T = p.T * steps / w["steps"]
+        t0 = time.perf_counter()
+        rc = L.orc_price_grids(C.byref(ps), lvc.ctypes.data_as(C.POINTER(C.c_int32)),
+                               coef.ctypes.data_as(C.POINTER(C.c_double)), len(sel), C.byref(sc), steps,
+                               threads, units.ctypes.data_as(C.POINTER(C.c_double)),
+                               out.ctypes.data_as(C.POINTER(C.c_double)))
+        assert rc == 0
+        return time.perf_counter() - t0
+
+    t6 = run(6)
+    steps = int(min(w["steps"], max(6, round(6 * target_seconds / max(t6, 1e-3)))))
+    dt = run(steps)
     su = float(sum(1 << int(s) for s in sel.sum(axis=1))) * 2 * steps
     return {"value": su / dt, "unit": "stage-updates/s", "cores": threads, "kind": "oracle",
             "seconds": dt,
