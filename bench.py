@@ -369,6 +369,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-ct6", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--only", choices=["serving", "ct6", "surrogate"], default=None,
+                    help="run one secondary section alone and print its JSON (profiling runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/hbm_traffic_ct4.json from two rocprofv3 --pmc runs")
     ap.add_argument("--pmc-precision", default="fp64")
@@ -389,6 +391,10 @@ def main():
     from paper_2408_00559_amd import inputs as I
     from paper_2408_00559_amd.solver import Plan
 
+    if args.only:
+        run = {"serving": run_serving, "ct6": run_ct6, "surrogate": run_surrogate}[args.only]
+        print(json.dumps({args.only: run(torch, Plan)}), flush=True)
+        return
     w = I.workload_ct4()
     copy_gbps = copy_bandwidth(torch)
     f64 = None if args.no_fp64 else run_form(torch, Plan, w, "fp64", args.steps, args.warmup)
