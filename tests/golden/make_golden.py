@@ -3,6 +3,7 @@
 Calls only the CPU oracle (oracle/) and the input definitions (paper_2408_00559_amd/inputs.py).
 Usage:  python tests/golden/make_golden.py ct4 [threads]      (d=4, n=7, psi=3, 100 steps, FP64)
         python tests/golden/make_golden.py batch4 [threads]   (first 16 of the 512 seeded instances)
+        python tests/golden/make_golden.py ct6 [threads]      (d=6, n=8, psi=1: sampled grids, 400 steps)
 """
 import json
 import os
@@ -54,6 +55,34 @@ def run_batch4(threads, count=16):
     _dump(out, "batch4_first16_fp64.json")
 
 
+CT6_SAMPLE = [[9, 1, 1, 1, 1, 1], [1, 1, 1, 1, 1, 9], [1, 1, 9, 1, 1, 1], [3, 3, 2, 2, 2, 2],
+              [4, 1, 1, 1, 1, 1], [1, 1, 1, 2, 2, 2]]
+
+
+def run_ct6(threads):
+    """Sampled component grids of the d = 6 workload: u_l(x_eval) after the fine run of the
+    Richardson pair (2 * 200 steps), one oracle solve per grid."""
+    from concurrent.futures import ThreadPoolExecutor
+    w = I.workload_ct6()
+    p = w["problems"][0]
+    lv, _ = oracle.ct_grids(p.d, w["grid"].n, w["grid"].psi)
+    listed = set(tuple(int(v) for v in row) for row in lv)
+    assert all(tuple(s) in listed for s in CT6_SAMPLE)
+    steps = 2 * w["steps"]
+    t = time.time()
+
+    def one(levels):
+        return float(oracle.interpolate(p, levels, oracle.solve_grid(p, levels, steps)))
+
+    with ThreadPoolExecutor(max_workers=max(1, threads or len(CT6_SAMPLE))) as ex:
+        vals = list(ex.map(one, CT6_SAMPLE))
+    out = dict(workload=w["name"], steps=steps, unit_levels=CT6_SAMPLE, unit_values=vals,
+               oracle_seconds=time.time() - t,
+               note="FP64 CPU oracle, sampled component grids after the fine Richardson run, "
+                    "written by tests/golden/make_golden.py")
+    _dump(out, "ct6_n8_psi1_sampled_fp64.json")
+
+
 def reformat(name):
     """Rewrite an existing file in the layout above (values unchanged)."""
     _dump(json.load(open(os.path.join(HERE, name))), name)
@@ -65,4 +94,4 @@ if __name__ == "__main__":
         reformat(sys.argv[2])
         sys.exit(0)
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    {"ct4": run_ct4, "batch4": run_batch4}[which](threads)
+    {"ct4": run_ct4, "batch4": run_batch4, "ct6": run_ct6}[which](threads)

@@ -7,6 +7,8 @@
   sampled component grids (the most elongated ones in each axis).
 * 512 seeded d = 4 instances (n = 6, psi = 1): the first 16 prices against the oracle's stored
   values, FP64 and FP32, in the serving configuration (autotuned schedule, graph replay).
+* d = 6, n = 8, psi = 1 with the Richardson pair (2,975 grids): u_l(x_eval) of sampled grids after
+  the solve against the oracle's stored values (tests/golden/ct6_n8_psi1_sampled_fp64.json).
 """
 import json
 import os
@@ -117,3 +119,26 @@ def test_batch4_serving_configuration(precision, tol):
     err = np.abs(prices[:len(ref)] - ref) / np.abs(ref)
     assert err.max() < tol, (err.max(), plan.schedule())
     assert np.all(np.isfinite(prices))
+
+
+CT6 = os.path.join(HERE, "golden", "ct6_n8_psi1_sampled_fp64.json")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_ct6_full_size_sampled_grids(precision, tol):
+    """d = 6, n = 8, psi = 1 (2,975 grids) with the Richardson pair, in the benchmark's configuration
+    (autotuned schedule, graph replay): after the solve, u_l(x_eval) of the fine run on sampled grids
+    (longest axis 1, 3 and V, a balanced grid, two of the coarsest layer) against the oracle's stored
+    values."""
+    g = _golden(CT6)
+    w = I.workload_ct6()
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision=precision, richardson=True, device=DEV)
+    autotune.tune(plan, steps=1, reps=1, use_cache=False)
+    plan.use_graph(True)
+    plan.solve()
+    vals = plan.unit_values().cpu().numpy()
+    index = {tuple(u["levels"]): i for i, u in enumerate(plan.units())}
+    scale = max(abs(v) for v in g["unit_values"])
+    for lv, ref in zip(g["unit_levels"], g["unit_values"]):
+        got = vals[index[tuple(lv)]]
+        assert abs(got - ref) / scale < tol, (lv, got, ref)
