@@ -204,3 +204,27 @@ def test_unit_offsets_keep_axis0_lines_inside_operator_blocks(d, n, psi, count):
         end = off.value + (1 << sum(lv[i] for i in range(d)))
     assert end * (8 if info.precision == L.FP64 else 4) <= info.vector_bytes
     L.lib().amf_plan_destroy(h)
+
+
+def test_empty_and_null_arguments():
+    """No problems, null descriptors and null outputs are rejected with AMF_E_INVALID; destroying a
+    null plan is a no-op; a zero-level axis (M = 1) is a valid, degenerate grid."""
+    lib = L.lib()
+    p = I.draw_instances(1, seed=2, d=3)[0]
+    gs = S.grid_struct(I.combination(4, 1))
+    sc = S.scheme_amfrw2()
+    h = C.c_void_p()
+    arr = (L.AmfProblem * 1)(S.problem_struct(p))
+    assert lib.amf_plan_create(arr, 0, C.byref(gs), C.byref(sc), L.FP64, 4, 0, C.byref(h)) == L.E_INVALID
+    assert lib.amf_plan_create(None, 1, C.byref(gs), C.byref(sc), L.FP64, 4, 0, C.byref(h)) == L.E_INVALID
+    assert lib.amf_plan_create(arr, 1, None, C.byref(sc), L.FP64, 4, 0, C.byref(h)) == L.E_INVALID
+    assert lib.amf_plan_create(arr, 1, C.byref(gs), C.byref(sc), L.FP64, 4, 0, None) == L.E_INVALID
+    assert len(lib.amf_last_error()) > 0
+    st, h = _create([p], I.full_grid([5, 0, 3]))
+    assert st == L.OK
+    info = L.AmfPlanInfo()
+    L.check(lib.amf_plan_info_get(h, C.byref(info)))
+    assert (info.n_units, info.inner_points) == (1, 1 << 8)
+    assert lib.amf_combine(h, None, None) in (L.E_INVALID, L.E_STATE)
+    lib.amf_plan_destroy(h)
+    lib.amf_plan_destroy(None)
