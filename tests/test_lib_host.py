@@ -228,3 +228,15 @@ def test_empty_and_null_arguments():
     assert lib.amf_combine(h, None, None) in (L.E_INVALID, L.E_STATE)
     lib.amf_plan_destroy(h)
     lib.amf_plan_destroy(None)
+
+
+def test_header_is_plain_c():
+    """include/amfrw.h compiles as C99 and as C++17 without warnings (plain types only)."""
+    import shutil
+    import subprocess
+    for cc, args in (("gcc", ["-std=c99", "-x", "c"]), ("g++", ["-std=c++17", "-x", "c++"])):
+        if shutil.which(cc) is None:
+            pytest.skip("%s not available" % cc)
+        r = subprocess.run([cc, *args, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", HEADER],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
