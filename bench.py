@@ -185,7 +185,11 @@ def run_serving(torch, Plan, batches=10):
     p64 = ref64.price().cpu().numpy()
     del ref64
     torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp32", device="cuda:0")
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
     tuned = autotune.tune(plan, steps=1, reps=1)
     plan.use_graph(True)
     prices = torch.empty(n, dtype=torch.float64, device="cuda:0")
@@ -215,6 +219,7 @@ def run_serving(torch, Plan, batches=10):
            "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                          "min": float(lat.min()), "max": float(lat.max())},
            "max_rel_err_vs_fp64": float(rel.max()), "max_rel_err_vs_oracle_first16": rel_oracle,
+           "plan_setup_s": setup_s,
            "schedule": plan.schedule(), "autotune_cached": tuned.get("cached")}
     del plan
     torch.cuda.empty_cache()

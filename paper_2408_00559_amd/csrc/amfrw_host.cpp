@@ -3,8 +3,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "amfrw.h"
@@ -321,11 +323,20 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         }
         P->n_units = (int)nu64;
 
-        // coefficient tables: per problem a constant block, then (axis, level) blocks
-        std::vector<double> facs[2];
-        for (int p = 0; p < n_probs; ++p) {
-            const amf_problem& pr = probs[p];
+        // Per problem (independent, built on host threads): a constant block and (axis, level)
+        // coefficient blocks, the Thomas factor tables of both runs, and each grid's table
+        // indices, all relative to the problem's own buffers; then concatenated in problem order.
+        struct ProbTables {
             ProbDev pd{};
+            std::vector<double> tab;
+            std::vector<double> fac[2];
+            std::vector<int64_t> unit_tab, unit_fac;   // [g * d + i], relative
+        };
+        std::vector<ProbTables> pt((size_t)n_probs);
+        auto build_problem = [&](int p) {
+            const amf_problem& pr = probs[p];
+            ProbTables& T = pt[(size_t)p];
+            ProbDev& pd = T.pd;
             for (int i = 0; i < d; ++i) {
                 pd.xmax[i] = pr.x_max[i];
                 pd.xeval[i] = pr.x_eval[i];
@@ -334,65 +345,108 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             pd.K = pr.strike;
             pd.discount = pr.discount;
             pd.payoff = pr.payoff;
-            pd.cst = (int32_t)P->tabd.size();
+            pd.cst = 0;
             pd.unit_begin = p * ng;
             pd.unit_end = (p + 1) * ng;
-            std::vector<double> c(CST_SIZE, 0.0);
+            std::vector<double>& tab = T.tab;
+            tab.assign(CST_SIZE, 0.0);
             for (int i = 0; i < d - 1; ++i) {
-                for (int k = 0; k < d - 1; ++k) c[CST_RHO + i * MAXD + k] = pr.rho[i * RHO_LD + k];
-                c[CST_SPHI + i] = pr.sigma * pr.phi[i];
+                for (int k = 0; k < d - 1; ++k) tab[CST_RHO + i * MAXD + k] = pr.rho[i * RHO_LD + k];
+                tab[CST_SPHI + i] = pr.sigma * pr.phi[i];
             }
             const double dt = pr.maturity / (double)n_steps;
             for (int run = 0; run < 2; ++run) {
                 const double h = run == 0 ? dt : 0.5 * dt;
-                c[CST_RUN + 3 * run + 0] = h;
-                c[CST_RUN + 3 * run + 1] = scheme->nu * h;
-                c[CST_RUN + 3 * run + 2] = scheme->theta * h;
+                tab[CST_RUN + 3 * run + 0] = h;
+                tab[CST_RUN + 3 * run + 1] = scheme->nu * h;
+                tab[CST_RUN + 3 * run + 2] = scheme->theta * h;
             }
-            P->tabd.insert(P->tabd.end(), c.begin(), c.end());
             // axis tables for every level in use on that axis
-            std::vector<int32_t> blk_of[MAXD];
+            std::vector<int64_t> blk_of[MAXD];
             for (int i = 0; i < d; ++i) blk_of[i].assign(17, -1);
+            T.unit_tab.assign((size_t)ng * d, 0);
             for (int g = 0; g < ng; ++g)
                 for (int i = 0; i < d; ++i) {
                     const int L = glv[g][i];
                     if (blk_of[i][L] < 0) {
-                        if (P->tabd.size() > (size_t)INT32_MAX / 2) throw std::bad_alloc();
-                        blk_of[i][L] = (int32_t)P->tabd.size();
-                        append_axis_table(P->tabd, pr, i, L);
+                        blk_of[i][L] = (int64_t)tab.size();
+                        append_axis_table(tab, pr, i, L);
                     }
+                    T.unit_tab[(size_t)g * d + i] = blk_of[i][L];
                 }
-            P->probdev.push_back(pd);
             // Thomas factors per (axis, level, V level) in use, both runs (axis 0: the fused solve)
             std::vector<std::vector<int64_t>> fac_of(d, std::vector<int64_t>(17 * 17, -1));
             // FP64 weights delta_r = d_ax / h_ax^2 along a line (as the coefficient tables hold them)
+            std::vector<double> dl;
             auto delta_of = [&](int ax, int L, int LV, int jv, const std::vector<double>& t,
-                                const std::vector<double>& tv) {
+                                const std::vector<double>& tv) -> const std::vector<double>& {
                 const int M = 1 << L, MV = 1 << LV;
-                std::vector<double> dl(M);
+                dl.resize(M);
                 for (int r = 0; r < M; ++r)
                     dl[r] = (ax < d - 1) ? t[r] * tv[jv] : tv[MV] * tv[r];
                 return dl;
             };
-            std::vector<int64_t> unit_fac((size_t)ng * d, 0);
+            T.unit_fac.assign((size_t)ng * d, 0);
+            std::vector<double> t, tv;
             for (int g = 0; g < ng; ++g)
                 for (int i = 0; i < d; ++i) {
                     const int L = glv[g][i], LV = glv[g][d - 1];
                     const int key = (i < d - 1) ? L * 17 + LV : L * 17 + L;
                     if (fac_of[i][key] < 0) {
-                        fac_of[i][key] = (int64_t)facs[0].size();
+                        fac_of[i][key] = (int64_t)T.fac[0].size();
                         const int nlines = (i < d - 1) ? (1 << LV) : 1;
-                        std::vector<double> t, tv;
+                        t.clear();
+                        tv.clear();
                         append_axis_table(t, pr, i, L);
                         append_axis_table(tv, pr, d - 1, LV);
                         for (int run = 0; run < 2; ++run) {
                             const double h = run == 0 ? pr.maturity / (double)n_steps : 0.5 * pr.maturity / (double)n_steps;
                             for (int jv = 0; jv < nlines; ++jv)
-                                append_factors(facs[run], delta_of(i, L, LV, jv, t, tv), scheme->nu * h);
+                                append_factors(T.fac[run], delta_of(i, L, LV, jv, t, tv), scheme->nu * h);
                         }
                     }
-                    unit_fac[(size_t)g * d + i] = fac_of[i][key];
+                    T.unit_fac[(size_t)g * d + i] = fac_of[i][key];
                 }
+        };
+        {
+            // problems on up to 16 host threads; any exception is rethrown here
+            const int nt = std::max(1, std::min<int>({n_probs, 16, (int)std::max(1u, std::thread::hardware_concurrency())}));
+            std::vector<std::exception_ptr> errs((size_t)nt);
+            std::vector<std::thread> pool;
+            for (int w = 0; w < nt; ++w)
+                pool.emplace_back([&, w] {
+                    try {
+                        for (int p = w; p < n_probs; p += nt) build_problem(p);
+                    } catch (...) {
+                        errs[(size_t)w] = std::current_exception();
+                    }
+                });
+            for (std::thread& th : pool) th.join();
+            for (std::exception_ptr& e : errs)
+                if (e) std::rethrow_exception(e);
+        }
+        // concatenate in problem order (buffers sized once); units in problem order, grid order
+        // within a problem; the run-1 factor tables follow all run-0 tables
+        int64_t ntab = 0, nfac = 0;
+        for (const ProbTables& T : pt) {
+            ntab += (int64_t)T.tab.size();
+            nfac += (int64_t)T.fac[0].size();
+        }
+        if (ntab > (int64_t)INT32_MAX / 2 || nfac > (int64_t)INT32_MAX) throw std::bad_alloc();
+        P->tabd.resize((size_t)ntab);
+        P->facd.resize((size_t)(2 * nfac));
+        P->fac_run = nfac;
+        P->units.reserve((size_t)P->n_units + 1);
+        P->coef.reserve((size_t)P->n_units);
+        P->probdev.reserve((size_t)n_probs);
+        int64_t tab0 = 0, fac0 = 0;
+        for (int p = 0; p < n_probs; ++p) {
+            ProbTables& T = pt[(size_t)p];
+            T.pd.cst = (int32_t)tab0;
+            std::copy(T.tab.begin(), T.tab.end(), P->tabd.begin() + tab0);
+            std::copy(T.fac[0].begin(), T.fac[0].end(), P->facd.begin() + fac0);
+            std::copy(T.fac[1].begin(), T.fac[1].end(), P->facd.begin() + nfac + fac0);
+            P->probdev.push_back(T.pd);
             for (int g = 0; g < ng; ++g) {
                 UnitDev U{};
                 // offsets are multiples of min(M_0, 1024) as well, so that node blocks of the
@@ -404,9 +458,10 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 int ls = 0;
                 for (int i = 0; i < d; ++i) {
                     U.lv[i] = (int8_t)glv[g][i];
-                    U.tab[i] = blk_of[i][glv[g][i]];
-                    if (unit_fac[(size_t)g * d + i] > INT32_MAX) throw std::bad_alloc();
-                    U.fac[i] = (int32_t)unit_fac[(size_t)g * d + i];
+                    U.tab[i] = (int32_t)(tab0 + T.unit_tab[(size_t)g * d + i]);
+                    const int64_t f = fac0 + T.unit_fac[(size_t)g * d + i];
+                    if (f > INT32_MAX) throw std::bad_alloc();
+                    U.fac[i] = (int32_t)f;
                     ls += glv[g][i];
                 }
                 U.lsum = ls;
@@ -415,14 +470,16 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 P->total += (int64_t)1 << ls;
                 P->inner += (int64_t)1 << ls;
             }
+            tab0 += (int64_t)T.tab.size();
+            fac0 += (int64_t)T.fac[0].size();
+            std::vector<double>().swap(T.tab);
+            std::vector<double>().swap(T.fac[0]);
+            std::vector<double>().swap(T.fac[1]);
         }
         P->total = (P->total + UNIT_ALIGN - 1) / UNIT_ALIGN * UNIT_ALIGN;
         UnitDev sentinel{};
         sentinel.off = P->total;
         P->units.push_back(sentinel);
-        P->fac_run = (int64_t)facs[0].size();
-        P->facd = std::move(facs[0]);
-        P->facd.insert(P->facd.end(), facs[1].begin(), facs[1].end());
 
         // node blocks -> first unit
         auto block_table = [&](int64_t per, std::vector<int32_t>& tbl) {
@@ -451,8 +508,9 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->res_lds_len = (1 << max_lsum) + ((1 << max_lsum) >> 4);
         const int rmax = precision == AMF_FP64 ? STENCIL_R_F64 : STENCIL_R_F32;
         P->stencil_r = std::min(rmax, min_m0) >= 4 ? 4 : (std::min(rmax, min_m0) >= 2 ? 2 : 1);
-        // per axis: units ordered by M_axis, line offsets, blocks that never mix line lengths
-        for (int ax = 0; ax < d; ++ax) {
+        // per axis (one host thread each): units ordered by M_axis, line offsets, blocks that
+        // never mix line lengths
+        auto build_axis = [&](int ax) {
             std::vector<int32_t>& ord = P->ax_units[ax];
             ord.resize(P->n_units);
             for (int u = 0; u < P->n_units; ++u) ord[u] = u;
@@ -533,6 +591,21 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 }
                 k0 = k1;
             }
+        };
+        {
+            std::vector<std::exception_ptr> errs((size_t)d);
+            std::vector<std::thread> pool;
+            for (int ax = 0; ax < d; ++ax)
+                pool.emplace_back([&, ax] {
+                    try {
+                        build_axis(ax);
+                    } catch (...) {
+                        errs[(size_t)ax] = std::current_exception();
+                    }
+                });
+            for (std::thread& th : pool) th.join();
+            for (std::exception_ptr& e : errs)
+                if (e) std::rethrow_exception(e);
         }
 
         // workspace layout
