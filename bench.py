@@ -127,7 +127,11 @@ def copy_bandwidth(torch, nbytes=2 << 30, reps=10):
 
 def run_form(torch, Plan, w, precision, steps, warmup, tune=True):
     from paper_2408_00559_amd import autotune
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
     plan = Plan(w["problems"], w["grid"], w["steps"], precision=precision, device="cuda:0")
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t_setup
     tuned = autotune.tune(plan, steps=2, reps=1) if tune else None
     prices = torch.empty(len(w["problems"]), dtype=torch.float64, device="cuda:0")
     for _ in range(warmup):
@@ -161,6 +165,7 @@ def run_form(torch, Plan, w, precision, steps, warmup, tune=True):
                       "GBps": (v["algo_bytes"] / (v["ms"] * 1e-3) / 1e9) if v["ms"] > 0 else None}
                   for k, v in kstats.items() if v["launches"]}
     out = dict(value=su / sec, sec_per_solve=sec, price=price, stage_updates=su, roofline=roof,
+               plan_setup_s=t_setup,
                kernels=per_kernel, units=plan.n_units, inner_points=plan.inner_points,
                schedule=plan.schedule(), autotune=(None if tuned is None else
                                                    {"trials": tuned.get("trials"), "cached": tuned.get("cached")}))
@@ -434,6 +439,7 @@ def main():
         "kernels": f64["kernels"],
         "schedule": f64["schedule"],
         "autotune": f64["autotune"],
+        "plan_setup_s": f64["plan_setup_s"],
         "copy_GBps": copy_gbps,
     }
     if f32 is not None:
