@@ -375,3 +375,17 @@ def test_fused_axis0_schedule(name, precision, tol):
         p_fused = plan.price().cpu().numpy()
         plan.use_graph(False)
         assert np.allclose(p_fused, p_plain, rtol=1e-12 if precision == "fp64" else 1e-5), r
+
+
+def test_unstable_configuration_blows_up_like_the_oracle():
+    """Failure path forced from the host: nu = 0.05 (far below theta) makes the step unstable; the
+    GPU price is non-finite or huge, as the oracle's is, and agrees with it while finite."""
+    from paper_2408_00559_amd.solver import scheme_amfrw2
+    p = I.workload_fg2d()["problems"][0]
+    grid = I.full_grid([6, 6])
+    plan = Plan([p], grid, 5, scheme=scheme_amfrw2(0.05), device=DEV)
+    got = float(plan.price().cpu().numpy()[0])
+    ref = oracle.price(p, grid, 5, scheme=oracle.scheme_amfrw2(0.05))
+    assert not np.isfinite(got) or abs(got) > 1e6, got
+    if np.isfinite(got) and np.isfinite(ref):
+        assert abs(got - ref) / abs(ref) < 1e-6, (got, ref)

@@ -113,3 +113,9 @@ def test_surrogate_gain_with_fallback():
     # the calibrated error estimate is an honest filter: served prices meet the tolerance up to the
     # calibration quantile
     assert np.quantile(rel[served], 0.9) < tol, np.quantile(rel[served], 0.9)
+    # requests outside the training box (maturity beyond its range) always go to the solver
+    outside = I.draw_instances(8, seed=53, d=4, T_range=(2.0, 2.5), lam_range=(0.05, 0.3))
+    po, used_o, _, _ = sur.price(outside, tol=1.0)
+    assert used_o.all()
+    yo = S.solver_prices(outside, grid, steps)
+    assert np.max(np.abs(po - yo) / np.abs(yo)) < 1e-6

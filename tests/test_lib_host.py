@@ -240,3 +240,18 @@ def test_header_is_plain_c():
         r = subprocess.run([cc, *args, "-Wall", "-Wextra", "-Werror", "-fsyntax-only", HEADER],
                            capture_output=True, text=True)
         assert r.returncode == 0, r.stderr
+
+
+def test_bind_rejects_small_or_misaligned_workspace():
+    """amf_plan_bind checks size and alignment before touching the memory."""
+    lib = L.lib()
+    p = I.draw_instances(1, seed=4, d=3)[0]
+    st, h = _create([p], I.combination(4, 1))
+    info = L.AmfPlanInfo()
+    L.check(lib.amf_plan_info_get(h, C.byref(info)))
+    fake = C.c_void_p(1 << 40)                     # never dereferenced: the checks fail first
+    assert lib.amf_plan_bind(h, fake, info.workspace_bytes - 1, None) == L.E_INVALID
+    assert "too small" in lib.amf_last_error().decode()
+    assert lib.amf_plan_bind(h, C.c_void_p((1 << 40) + 64), info.workspace_bytes, None) == L.E_INVALID
+    assert lib.amf_plan_bind(h, None, info.workspace_bytes, None) == L.E_INVALID
+    lib.amf_plan_destroy(h)

@@ -413,3 +413,13 @@ def test_swaption_payoff_is_positive_swap_value(orc):
             irs += bond * p.tau[i] * (F[i] - p.K)
         x = list(F) + [1.0]
         assert abs(orc.payoff(p, x) - max(irs, 0.0)) < 1e-15
+
+
+def test_small_nu_is_unstable(orc):
+    """The AMF parameter matters: with nu far below theta the scheme is unstable at the step sizes
+    where nu = theta is not (the price then grows without bound); a control for the failure path."""
+    p = I.workload_fg2d()["problems"][0]
+    good = orc.price(p, I.full_grid([6, 6]), 5)
+    bad = orc.price(p, I.full_grid([6, 6]), 5, scheme=orc.scheme_amfrw2(0.05))
+    assert 0.0 < good < 0.05
+    assert not np.isfinite(bad) or abs(bad) > 1e6, bad
