@@ -146,8 +146,8 @@ struct SweepArgs {
 
 // Unit-resident schedule: one workgroup of RES_BLOCK threads per unit, the whole time loop in LDS.
 constexpr int RES_BLOCK = 128;
-constexpr int RES_MAX_LSUM_F32 = 11;   // units up to 2048 points (5 padded FP32 vectors: 43.5 KB)
-constexpr int RES_MAX_LSUM_F64 = 10;   // units up to 1024 points (5 padded FP64 vectors: 43.5 KB)
+constexpr int RES_MAX_LSUM_F32 = 11;   // units up to 2048 points (4 padded FP32 vectors: 34.8 KB)
+constexpr int RES_MAX_LSUM_F64 = 10;   // units up to 1024 points (4 padded FP64 vectors: 34.8 KB)
 
 struct ResArgs {
     void* W;              // solution W (global), read at entry and written at exit

@@ -1051,9 +1051,9 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArg
 }
 
 // ------------------------------------------------------------------------------------------------
-// Unit-resident schedule: one workgroup per unit advances it by n AMFR-W steps with W, K1, two work
-// vectors and the Thomas scratch in LDS; only W (in and out) and F(g) (read per stage) touch
-// global memory.  LDS arrays are padded by one element per 16 (li) so that lanes walking lines of
+// Unit-resident schedule: one workgroup per unit advances it by n AMFR-W steps with W, K1 and two
+// work vectors in LDS; only W (in and out), F(g) (read per stage) and the tabulated Thomas
+// factors touch global memory.  LDS arrays are padded by one element per 16 (li) so that lanes walking lines of
 // any axis hit distinct banks.
 __device__ __forceinline__ int li(int n) { return n + (n >> 4); }
 
@@ -1175,51 +1175,50 @@ __device__ __forceinline__ void res_axis0(const ResGeom<D>& G, const UnitDev& U,
 // Solves along a strided axis (in place on `io`), Thomas with c' in the LDS scratch; with `upd`,
 // the result x updates W += b1 K1 + b2 x instead of being stored.
 template <typename T, int D>
-__device__ __forceinline__ void res_strided(const ResGeom<D>& G, const UnitDev& U, const T* tab, T nudt, int ax,
-                                            const T* in, T* io, T* sC, bool upd, T* sW, const T* sK, T b1, T b2)
+__device__ __forceinline__ void res_strided(const ResGeom<D>& G, const UnitDev& U, const T* fac, int ax,
+                                            const T* in, T* io, bool upd, T* sW, const T* sK, T b1, T b2)
 {
+    // one thread per line, Thomas with the plan's tabulated factors of the line (inv, a inv, c'
+    // of (I - nu dt A_ax) for this unit's levels and the line's j_V, as the streaming sweeps use)
     const int Mi = G.M[ax], Si = G.S[ax], E = 1 << Si;
     const int lines = G.Pn / Mi;
     const bool isV = ax == D - 1;
-    const T* td = tab + U.tab[ax];
-    const T* vs = tab + U.tab[D - 1];
-    const T tdV = vs[G.MV];
+    const T* fa = fac + U.fac[ax];
     for (int line = threadIdx.x; line < lines; line += RES_BLOCK) {
         const int lo = line & (E - 1), hi = line >> Si;
         const int base = lo + (hi << (Si + U.lv[ax]));
-        const T cm = isV ? tdV : vs[(base >> G.SV) & (G.MV - 1)];
-        T cprev = T(0), dprev = T(0);
+        const T* f = isV ? fa : fa + (int64_t)((base >> G.SV) & (G.MV - 1)) * 3 * Mi;
+        T dprev = T(0);
+#pragma unroll 4
         for (int r = 0; r < Mi; ++r) {
             const int idx = li(base + r * E);
-            const T del = isV ? cm * vs[r] : td[r] * cm;
-            const T nd = nudt * del;
-            const T b = T(1) + T(2) * nd;
-            const T a = (r == 0) ? T(0) : ((r == Mi - 1) ? -T(2) * nd : -nd);
-            const T c = (r == Mi - 1) ? T(0) : -nd;
-            const T inv = T(1) / (b - a * cprev);
-            cprev = c * inv;
-            dprev = (in[idx] - a * dprev) * inv;
-            sC[idx] = cprev;
+            dprev = in[idx] * f[r] - f[Mi + r] * dprev;
             io[idx] = dprev;
         }
-        T x = dprev;
-        for (int r = Mi - 1; r >= 0; --r) {
+        T x = dprev;                            // c'_{M-1} = 0: x_{M-1} = d'_{M-1}
+        if (upd) {
+            const int idx = li(base + (Mi - 1) * E);
+            sW[idx] = sW[idx] + b1 * sK[idx] + b2 * x;
+        }
+#pragma unroll 4
+        for (int r = Mi - 2; r >= 0; --r) {
             const int idx = li(base + r * E);
-            if (r < Mi - 1) x = io[idx] - sC[idx] * x;
+            x = io[idx] - f[2 * Mi + r] * x;
             if (upd) sW[idx] = sW[idx] + b1 * sK[idx] + b2 * x;
             else io[idx] = x;
         }
     }
 }
 
+// The AMF chain (I - nu dt A_1) .. (I - nu dt A_d) on LDS vectors: axis 0 reads src, the others
+// work in place on dst; with upd the last solve ends in W += b1 K1 + b2 K2.
 template <typename T, int D>
-__device__ __forceinline__ void res_chain(const ResGeom<D>& G, const UnitDev& U, const T* tab, T nudt,
-                                          const T* src, T* dst, T* sC, bool upd, T* sW, const T* sK, T b1, T b2)
+__device__ __forceinline__ void res_chain(const ResGeom<D>& G, const UnitDev& U, const T* fac,
+                                          const T* src, T* dst, bool upd, T* sW, const T* sK, T b1, T b2)
 {
-    // every axis by one thread per line with c' in the LDS scratch (axis 0 reads src, then in place)
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        res_strided<T, D>(G, U, tab, nudt, ax, ax == 0 ? src : dst, dst, sC, upd && ax == D - 1, sW, sK, b1, b2);
+        res_strided<T, D>(G, U, fac, ax, ax == 0 ? src : dst, dst, upd && ax == D - 1, sW, sK, b1, b2);
         __syncthreads();
     }
 }
@@ -1247,30 +1246,30 @@ __global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
     T* sK = sW + LP;
     T* sA = sK + LP;
     T* sB = sA + LP;
-    T* sC = sB + LP;
     T* Wg = (T*)A.W + U.off;
     const T* cGg = (const T*)A.cG + U.off;
     const T* tab = (const T*)P.tab;
     const T* cst = tab + P.probs[U.prob].cst;
-    const T dt = cst[CST_RUN + 3 * A.run], nudt = cst[CST_RUN + 3 * A.run + 1], thdt = cst[CST_RUN + 3 * A.run + 2];
+    const T dt = cst[CST_RUN + 3 * A.run], thdt = cst[CST_RUN + 3 * A.run + 2];
     const T a21 = (T)A.a21, q21 = (T)A.q21, b1 = (T)A.b1, b2 = (T)A.b2;
+    const T* fac = (const T*)P.fac + (int64_t)A.run * P.fac_run_stride;
     for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) sW[li(n)] = Wg[n];
     __syncthreads();
     for (int st = 0; st < A.nsteps; ++st) {
         // stage 1: K^(0) = dt F(Y); chain; refinement; chain -> K1
         res_stencil<T, D, OP_STAGE1>(G, U, tab, cst, dt, T(0), T(0), sW, nullptr, sA, cGg);
         __syncthreads();
-        res_chain<T, D>(G, U, tab, nudt, sA, sB, sC, false, sW, sK, b1, b2);
+        res_chain<T, D>(G, U, fac, sA, sB, false, sW, sK, b1, b2);
         res_stencil<T, D, OP_REFINE>(G, U, tab, cst, thdt, T(0), T(0), sB, nullptr, sA, cGg);
         __syncthreads();
-        res_chain<T, D>(G, U, tab, nudt, sA, sK, sC, false, sW, sK, b1, b2);
+        res_chain<T, D>(G, U, fac, sA, sK, false, sW, sK, b1, b2);
         // stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1; chain; refinement; chain ending in the update
         res_stencil<T, D, OP_STAGE2>(G, U, tab, cst, dt, a21, q21, sW, sK, sA, cGg);
         __syncthreads();
-        res_chain<T, D>(G, U, tab, nudt, sA, sB, sC, false, sW, sK, b1, b2);
+        res_chain<T, D>(G, U, fac, sA, sB, false, sW, sK, b1, b2);
         res_stencil<T, D, OP_REFINE>(G, U, tab, cst, thdt, T(0), T(0), sB, nullptr, sA, cGg);
         __syncthreads();
-        res_chain<T, D>(G, U, tab, nudt, sA, sB, sC, true, sW, sK, b1, b2);
+        res_chain<T, D>(G, U, fac, sA, sB, true, sW, sK, b1, b2);
     }
     for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) Wg[n] = sW[li(n)];
 }
@@ -1477,7 +1476,7 @@ template <typename T>
 static hipError_t resident_t(const DevPlan& P, const ResArgs& a, hipStream_t s)
 {
     dim3 g((unsigned)P.n_units), b(RES_BLOCK);
-    const size_t shm = (size_t)5 * a.lds_len * sizeof(T);
+    const size_t shm = (size_t)4 * a.lds_len * sizeof(T);
     switch (P.d) {
     case 2: hipLaunchKernelGGL((k_resident<T, 2>), g, b, shm, s, P, a); break;
     case 3: hipLaunchKernelGGL((k_resident<T, 3>), g, b, shm, s, P, a); break;
