@@ -31,6 +31,10 @@ def _cases():
         # one-thread-per-line memory path beyond it
         "very_long_v_axis": (I.workload_fg2d()["problems"], I.full_grid([2, 13])),
         "longest_v_axis": (I.workload_fg2d()["problems"], I.full_grid([1, 15])),
+        # unit-resident grids with fewer lines than workgroup threads (segmented solves in LDS)
+        "res_long_axis0": (I.workload_fg2d()["problems"], I.full_grid([9, 2])),
+        "res_long_v": (I.workload_fg2d()["problems"], I.full_grid([2, 9])),
+        "res_one_line": (I.workload_fg2d()["problems"], I.full_grid([10, 0])),
         "d3_full_ragged": (d3[:1], I.full_grid([7, 0, 8])),
         "d2_standard_ct": ([I.paper_caplet(sigma=0.3, phi=0.4)], I.combination(6, 0)),
         "d3_ct": (d3, I.combination(4, 1)),
@@ -302,7 +306,7 @@ def test_batched_instances(precision, tol):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
 @pytest.mark.parametrize("name", ["fg2d", "d2_standard_ct", "d3_ct", "d4_ct", "d5_ct", "d6_ct",
-                                  "long_rate_axis"])
+                                  "long_rate_axis", "res_long_axis0", "res_long_v", "res_one_line"])
 def test_resident_schedule(name, precision, tol):
     """a9: the unit-resident schedule (whole time loop in LDS, one workgroup per grid) against the
     oracle, element by element after two steps, for every d and for long axis-1 lines."""
@@ -327,7 +331,9 @@ def test_resident_schedule(name, precision, tol):
         return oracle.inner_view(Yf, lv)
 
     for (u, sl), r in zip(items, parallel(ref, items)):
-        assert rel_maxerr(Y[sl], r) < tol, (u, rel_maxerr(Y[sl], r))
+        m = 1 << max(u["levels"])             # line-solve rounding grows with the line length
+        t = max(tol, (4e-16 if precision == "fp64" else 2e-7) * m)
+        assert rel_maxerr(Y[sl], r) < t, (u, rel_maxerr(Y[sl], r))
     # a whole solve equals the streaming schedule's
     plan.set_schedule(resident=0)
     p_stream = plan.price().cpu().numpy()
