@@ -1172,14 +1172,14 @@ __device__ __forceinline__ void res_axis0(const ResGeom<D>& G, const UnitDev& U,
     }
 }
 
-// Solves along a strided axis (in place on `io`), Thomas with c' in the LDS scratch; with `upd`,
-// the result x updates W += b1 K1 + b2 x instead of being stored.
+// Solves along one axis of a resident unit (LDS `in` -> LDS `io`, in place when they coincide):
+// one thread per line, Thomas with the plan's tabulated factors of the line (inv, a inv, c' of
+// (I - nu dt A_ax) for this unit's levels and the line's j_V, as the streaming sweeps use); with
+// `upd` the result x updates W += b1 K1 + b2 x instead of being stored.
 template <typename T, int D>
 __device__ __forceinline__ void res_strided(const ResGeom<D>& G, const UnitDev& U, const T* fac, int ax,
                                             const T* in, T* io, bool upd, T* sW, const T* sK, T b1, T b2)
 {
-    // one thread per line, Thomas with the plan's tabulated factors of the line (inv, a inv, c'
-    // of (I - nu dt A_ax) for this unit's levels and the line's j_V, as the streaming sweeps use)
     const int Mi = G.M[ax], Si = G.S[ax], E = 1 << Si;
     const int lines = G.Pn / Mi;
     const bool isV = ax == D - 1;
