@@ -255,3 +255,14 @@ def test_bind_rejects_small_or_misaligned_workspace():
     assert lib.amf_plan_bind(h, C.c_void_p((1 << 40) + 64), info.workspace_bytes, None) == L.E_INVALID
     assert lib.amf_plan_bind(h, None, info.workspace_bytes, None) == L.E_INVALID
     lib.amf_plan_destroy(h)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU's share only: --gpus N > 1 exits with status 2 and says why."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
