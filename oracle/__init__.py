@@ -25,7 +25,7 @@ MAXS = 6
 
 
 class OrcProblem(C.Structure):
-    _fields_ = [("N", C.c_int32), ("model", C.c_int32), ("payoff", C.c_int32), ("pad_", C.c_int32),
+    _fields_ = [("N", C.c_int32), ("model", C.c_int32), ("payoff", C.c_int32), ("bc", C.c_int32),
                 ("beta", C.c_double), ("sigma", C.c_double),
                 ("alpha", C.c_double * MAXD), ("phi", C.c_double * MAXD), ("tau", C.c_double * MAXD),
                 ("rho", C.c_double * (MAXD * MAXD)), ("xmax", C.c_double * MAXD),
@@ -35,7 +35,7 @@ class OrcProblem(C.Structure):
 
 
 class OrcScheme(C.Structure):
-    _fields_ = [("s", C.c_int32), ("pad_", C.c_int32), ("a", C.c_double * (MAXS * MAXS)),
+    _fields_ = [("s", C.c_int32), ("wkind", C.c_int32), ("a", C.c_double * (MAXS * MAXS)),
                 ("q", C.c_double * (MAXS * MAXS)), ("b", C.c_double * MAXS),
                 ("theta", C.c_double), ("nu", C.c_double)]
 
@@ -68,6 +68,8 @@ def lib():
         L.orc_grid_size.restype = C.c_long
         L.orc_grid_size.argtypes = [C.c_int32, ip]
         L.orc_scheme_amfrw2.argtypes = [sp]
+        L.orc_scheme_theta_gs.argtypes = [C.c_double, C.c_int32, sp]
+        L.orc_solve_lower.argtypes = [pp, ip, C.c_double, dp, dp]
         L.orc_payoff.restype = C.c_double
         L.orc_payoff.argtypes = [pp, dp]
         L.orc_coefficients.argtypes = [pp, dp, dp, dp, dp]
@@ -98,6 +100,8 @@ def _ip(a):
 
 
 PAYOFF = {"caplet": 0, "swaption": 1, "gaussian": 2}
+BOUNDARY = {"neumann": 0, "dirichlet": 1}     # eq (bound1) / eq (bound1_0)
+W_AMF, W_LOWER = 0, 1
 
 
 def problem_struct(p, model: int = 0, D=None, c=None, gcenter=None, gwidth: float = 0.0) -> OrcProblem:
@@ -106,6 +110,7 @@ def problem_struct(p, model: int = 0, D=None, c=None, gcenter=None, gwidth: floa
     s.N = p.d
     s.model = model
     s.payoff = PAYOFF[p.payoff]
+    s.bc = BOUNDARY[getattr(p, "boundary", "neumann")]
     s.beta = p.beta
     s.sigma = p.sigma
     for i in range(p.d - 1):
@@ -142,10 +147,19 @@ def scheme_amfrw2(nu: float | None = None) -> OrcScheme:
     return s
 
 
-def scheme_generic(a, q, b, theta, nu) -> OrcScheme:
+def scheme_theta_gs(theta: float, stages: int) -> OrcScheme:
+    """theta-method with `stages` Gauss-Seidel sweeps as a W-method (Section 4.2): W = P, a = theta,
+    q = -1, b = 1."""
+    s = OrcScheme()
+    lib().orc_scheme_theta_gs(float(theta), int(stages), C.byref(s))
+    return s
+
+
+def scheme_generic(a, q, b, theta, nu, wkind: int = W_AMF) -> OrcScheme:
     s = OrcScheme()
     st = len(b)
     s.s = st
+    s.wkind = wkind
     for r in range(st):
         s.b[r] = b[r]
         for j in range(r):
@@ -209,6 +223,17 @@ def solve_axis(p, levels, axis, nudt, G, ps=None):
     Gc = np.ascontiguousarray(G, dtype=np.float64)
     K = np.empty_like(Gc)
     lib().orc_solve_axis(C.byref(ps), _ip(lv), int(axis), float(nudt), _dp(Gc), _dp(K))
+    return K
+
+
+def solve_lower(p, levels, thdt, R, ps=None):
+    """(I - thdt P) K = R with P the lower triangle (diagonal included) of the semi-discrete matrix,
+    by forward substitution in the theta_0 order (Section 4.2)."""
+    ps = ps or problem_struct(p)
+    lv = _levels(levels)
+    Rc = np.ascontiguousarray(R, dtype=np.float64)
+    K = np.empty_like(Rc)
+    lib().orc_solve_lower(C.byref(ps), _ip(lv), float(thdt), _dp(Rc), _dp(K))
     return K
 
 

@@ -33,12 +33,20 @@ enum { ORC_SABR_LMM = 0, ORC_CONST_COEF = 1 };
 /* Payoffs: caplet tau_1 (F_1-K)^+ (Section 2), swaption of Section 2 (the max{...} formula), and a
  * Gaussian bump exp(-|x-c|^2/(2w^2)) for the closed-form pin. */
 enum { ORC_CAPLET = 0, ORC_SWAPTION = 1, ORC_GAUSSIAN = 2 };
+/* Boundary conditions on the upper faces F_j = F_j^max of the rate axes (Section 2): homogeneous
+ * Neumann as in eq (bound1), or the payoff (Dirichlet) as in eq (bound1_0).  The lower faces carry the
+ * payoff and V = V^max is Neumann in both. */
+enum { ORC_BC_NEUMANN = 0, ORC_BC_DIRICHLET = 1 };
+/* Matrix W of the W-method (row-s): the AMF-refined W of eq (Wmat1), or the lower triangle P of the
+ * semi-discrete matrix (diagonal included), which turns a fixed number of Gauss-Seidel sweeps of the
+ * theta-method into a W-method (Section 4.2, eqs (thetamet) and (GS)). */
+enum { ORC_W_AMF = 0, ORC_W_LOWER = 1 };
 
 typedef struct {
     int32_t N;          /* spatial dimension: N-1 forward rates plus the volatility V            */
     int32_t model;      /* ORC_SABR_LMM or ORC_CONST_COEF                                         */
     int32_t payoff;     /* ORC_CAPLET, ORC_SWAPTION or ORC_GAUSSIAN                               */
-    int32_t pad_;
+    int32_t bc;         /* ORC_BC_NEUMANN (eq bound1) or ORC_BC_DIRICHLET (eq bound1_0)           */
     double beta, sigma; /* elasticity beta, volatility of volatility sigma                        */
     double alpha[ORC_MAXD], phi[ORC_MAXD], tau[ORC_MAXD];
     double rho[ORC_MAXD * ORC_MAXD];   /* rho[i*ORC_MAXD+j] between forward rates i, j             */
@@ -56,7 +64,7 @@ typedef struct {
 /* Generic s-stage AMFR-W method, eq (row-s) with the AMF-refined W of eq (Wmat1), stage form (amfrw). */
 typedef struct {
     int32_t s;
-    int32_t pad_;
+    int32_t wkind;      /* ORC_W_AMF or ORC_W_LOWER                                                */
     double a[ORC_MAXS * ORC_MAXS];  /* a[r*ORC_MAXS+j], j<r */
     double q[ORC_MAXS * ORC_MAXS];
     double b[ORC_MAXS];
@@ -93,6 +101,17 @@ static void decode(const orc_grid* G, long J, long* j)
         j[i] = c % (G->M[i] + 1);
         c = (c - j[i]) / (G->M[i] + 1);
     }
+}
+
+/* A node is Outer (its value is boundary data, its equation Y_J' = 0) when it lies on a lower face
+ * (Section 3), or, with the boundary conditions of eq (bound1_0), on the upper face of a rate axis. */
+static int is_outer(const orc_problem* P, const orc_grid* G, const long* j)
+{
+    for (int i = 0; i < G->N; ++i) {
+        if (j[i] == 0) return 1;
+        if (P->bc == ORC_BC_DIRICHLET && i < G->N - 1 && j[i] == G->M[i]) return 1;
+    }
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------------------------- */
@@ -185,10 +204,7 @@ static void eval_F(const orc_problem* P, const orc_grid* G, const double* Y, dou
     double x[ORC_MAXD], d[ORC_MAXD], m[ORC_MAXD * ORC_MAXD], a[ORC_MAXD];
     for (long J = 0; J < G->size; ++J) {
         decode(G, J, j);
-        int outer = 0;
-        for (int i = 0; i < N; ++i)
-            if (j[i] == 0) outer = 1;
-        if (outer) {          /* J in Outer: Y_J' = 0 */
+        if (is_outer(P, G, j)) {          /* J in Outer: Y_J' = 0 */
             out[J] = 0.0;
             continue;
         }
@@ -243,43 +259,108 @@ static void thomas(long n, const double* lo, const double* di, const double* up,
 }
 
 /* Lemma lema:ls: (I - nu dt A_i) K = G along axis i, as prod_{k != i} M_k tridiagonal systems of
- * size M_i (decomp1) with (delta_i)_J = (d_i)_J / h_i^2.  Outer entries: K_J = G_J (= 0). */
+ * size M_i (decomp1) with (delta_i)_J = (d_i)_J / h_i^2.  Outer entries: K_J = G_J (= 0).  With the
+ * Dirichlet faces of eq (bound1_0) a rate axis has the unknowns j_i = 1..M_i - 1 only: its systems
+ * have size M_i - 1 and the neighbour on the upper face is an Outer node (K = 0 there). */
 static void solve_axis(const orc_problem* P, const orc_grid* G, int ax, double nudt, const double* Gv,
                        double* K)
 {
     int N = G->N;
     long Mi = G->M[ax];
-    double *lo = malloc(sizeof(double) * Mi), *di = malloc(sizeof(double) * Mi);
-    double *up = malloc(sizeof(double) * Mi), *r = malloc(sizeof(double) * Mi);
-    double *xs = malloc(sizeof(double) * Mi), *cp = malloc(sizeof(double) * Mi);
-    double *dp = malloc(sizeof(double) * Mi);
+    const int dir = P->bc == ORC_BC_DIRICHLET && ax < N - 1;
+    long n = dir ? Mi - 1 : Mi;          /* unknowns along the line */
+    size_t cap = (size_t)(Mi > 0 ? Mi : 1);
+    double *lo = malloc(sizeof(double) * cap), *di = malloc(sizeof(double) * cap);
+    double *up = malloc(sizeof(double) * cap), *r = malloc(sizeof(double) * cap);
+    double *xs = malloc(sizeof(double) * cap), *cp = malloc(sizeof(double) * cap);
+    double *dp = malloc(sizeof(double) * cap);
     long j[ORC_MAXD];
     double x[ORC_MAXD];
     double h2 = G->h[ax] * G->h[ax];
     for (long J = 0; J < G->size; ++J) K[J] = Gv[J];
-    for (long J0 = 0; J0 < G->size; ++J0) {
+    for (long J0 = 0; n > 0 && J0 < G->size; ++J0) {
         decode(G, J0, j);
-        /* one system per multi-index with j_ax = 1 and every other j_l in 1..M_l */
+        /* one system per multi-index with j_ax = 1 and every other index on an unknown */
         if (j[ax] != 1) continue;
-        int outer = 0;
-        for (int i = 0; i < N; ++i)
-            if (j[i] == 0) outer = 1;
-        if (outer) continue;
-        for (long t = 1; t <= Mi; ++t) {
+        if (is_outer(P, G, j)) continue;
+        for (long t = 1; t <= n; ++t) {
             long J = J0 + (t - 1) * G->E[ax];
             for (int i = 0; i < N; ++i) x[i] = (double)j[i] * G->h[i];
             x[ax] = (double)t * G->h[ax];
             double delta = coef_diag(P, x, ax) / h2;
             long row = t - 1;
             di[row] = 1.0 + 2.0 * nudt * delta;
-            lo[row] = (t == 1) ? 0.0 : ((t == Mi) ? -2.0 * nudt * delta : -nudt * delta);
-            up[row] = (t == Mi) ? 0.0 : -nudt * delta;
+            /* the Neumann ghost Y_{J+E} = Y_{J-E} doubles the sub-diagonal of the last row */
+            lo[row] = (t == 1) ? 0.0 : ((t == Mi && !dir) ? -2.0 * nudt * delta : -nudt * delta);
+            up[row] = (t == n) ? 0.0 : -nudt * delta;
             r[row] = Gv[J];
         }
-        thomas(Mi, lo, di, up, r, xs, cp, dp);
-        for (long t = 1; t <= Mi; ++t) K[J0 + (t - 1) * G->E[ax]] = xs[t - 1];
+        thomas(n, lo, di, up, r, xs, cp, dp);
+        for (long t = 1; t <= n; ++t) K[J0 + (t - 1) * G->E[ax]] = xs[t - 1];
     }
     free(lo); free(di); free(up); free(r); free(xs); free(cp); free(dp);
+}
+
+/* Row J of the semi-discrete matrix A of Sketch 1 (F(Y) = A Y) for an inner node J with multi-index
+ * j: appends the column indices and values of its nonzero entries (with repeats: the Neumann ghost
+ * adds to J - E_i).  Up to 1 + 2N + 4 N(N-1)/2 entries. */
+static int row_of_A(const orc_problem* P, const orc_grid* G, long J, const long* j, long* col,
+                    double* val)
+{
+    int N = G->N, n = 0;
+    double x[ORC_MAXD], d[ORC_MAXD], m[ORC_MAXD * ORC_MAXD], a[ORC_MAXD];
+    for (int i = 0; i < N; ++i) x[i] = (double)j[i] * G->h[i];
+    orc_coefficients(P, x, d, m, a);
+    for (int i = 0; i < N; ++i) {
+        double c = d[i] / (G->h[i] * G->h[i]);
+        col[n] = J; val[n++] = -2.0 * c;
+        if (j[i] != G->M[i]) {
+            col[n] = J + G->E[i]; val[n++] = c;
+            col[n] = J - G->E[i]; val[n++] = c;
+        } else {
+            col[n] = J - G->E[i]; val[n++] = 2.0 * c;
+        }
+    }
+    for (int i = 0; i < N - 1; ++i)
+        for (int k = i + 1; k < N; ++k) {
+            if (j[i] == G->M[i] || j[k] == G->M[k]) continue;
+            double c = m[i * N + k] / (4.0 * G->h[i] * G->h[k]);
+            long Ei = G->E[i], Ek = G->E[k];
+            col[n] = J + Ei + Ek; val[n++] = c;
+            col[n] = J - Ei - Ek; val[n++] = c;
+            col[n] = J + Ei - Ek; val[n++] = -c;
+            col[n] = J - Ei + Ek; val[n++] = -c;
+        }
+    for (int i = 1; i < N - 1; ++i) {
+        if (j[i] == G->M[i]) continue;
+        double c = a[i] / (2.0 * G->h[i]);
+        col[n] = J + G->E[i]; val[n++] = c;
+        col[n] = J - G->E[i]; val[n++] = -c;
+    }
+    return n;
+}
+
+/* (I - thdt P) K = R by forward substitution in the order of theta_0 (Section 4.2, eq (GS)): P is the
+ * lower triangle of A including its diagonal, so K_J only needs the already computed K_{J'}, J' < J.
+ * Outer rows are identity rows (K_J = R_J, which is 0 for stage increments). */
+static void solve_lower(const orc_problem* P, const orc_grid* G, double thdt, const double* R, double* K)
+{
+    long j[ORC_MAXD], col[1 + 2 * ORC_MAXD + 2 * ORC_MAXD * ORC_MAXD];
+    double val[1 + 2 * ORC_MAXD + 2 * ORC_MAXD * ORC_MAXD];
+    for (long J = 0; J < G->size; ++J) {
+        decode(G, J, j);
+        if (is_outer(P, G, j)) {
+            K[J] = R[J];
+            continue;
+        }
+        int n = row_of_A(P, G, J, j, col, val);
+        double diag = 0.0, acc = R[J];
+        for (int e = 0; e < n; ++e) {
+            if (col[e] == J) diag += val[e];
+            else if (col[e] < J) acc += thdt * val[e] * K[col[e]];
+        }
+        K[J] = acc / (1.0 - thdt * diag);
+    }
 }
 
 /* Initial data (dis0): Y_J = g at every node, inner and outer. */
@@ -294,12 +375,14 @@ static void initial_data(const orc_problem* P, const orc_grid* G, double* Y)
     }
 }
 
-/* One step of the s-stage AMFR-W method, stage recursion (amfrw):
+/* One step of the s-stage W-method (row-s).  With the AMF-refined W of eq (Wmat1) every stage is the
+ * recursion of eq (amfrw):
  *   K_r^(0) = dt F(Y_n + sum_j a_rj K_j) + sum_j q_rj K_j
  *   (I - nu dt A_i) K_r^(i) = K_r^(i-1), i = 1..N
  *   Khat_r^(0) = 2 K_r^(0) - (I - theta dt F'(Y_n)) K_r^(N)      with F'(Y_n) K = F(K)  (linear F)
  *   (I - nu dt A_i) Khat_r^(i) = Khat_r^(i-1), i = 1..N
- *   K_r = Khat_r^(N);   Y_{n+1} = Y_n + sum_r b_r K_r   (row-s). */
+ *   K_r = Khat_r^(N);
+ * with W = P (Section 4.2) the stage is (I - theta dt P) K_r = K_r^(0).  Then Y_{n+1} = Y_n + sum_r b_r K_r. */
 static void amfrw_step(const orc_problem* P, const orc_grid* G, const orc_scheme* S, double dt,
                        double* Y, double** Kst, double* Z, double* K0, double* X, double* FX)
 {
@@ -315,6 +398,10 @@ static void amfrw_step(const orc_problem* P, const orc_grid* G, const orc_scheme
             double k0 = dt * FX[J];
             for (int jj = 0; jj < r; ++jj) k0 += S->q[r * ORC_MAXS + jj] * Kst[jj][J];
             K0[J] = k0;
+        }
+        if (S->wkind == ORC_W_LOWER) {
+            solve_lower(P, G, S->theta * dt, K0, Kst[r]);
+            continue;
         }
         memcpy(X, K0, sizeof(double) * n);
         for (int ax = 0; ax < G->N; ++ax) {
@@ -366,7 +453,7 @@ static double interpolate(const orc_grid* G, const double* Y, const double* x)
 
 /* ============================ exported entry points =========================================== */
 
-int32_t orc_abi(void) { return 3; }
+int32_t orc_abi(void) { return 4; }
 
 long orc_grid_size(int32_t N, const int32_t* levels)
 {
@@ -387,6 +474,31 @@ void orc_scheme_amfrw2(orc_scheme* S)
     S->b[1] = 3.0 / 4.0;
     S->theta = (3.0 + sqrt(3.0)) / 6.0;
     S->nu = S->theta;
+}
+
+/* theta-method with s Gauss-Seidel sweeps as a W-method (Section 4.2): W = P, a_rj = theta,
+ * q_rj = -1, b_r = 1. */
+void orc_scheme_theta_gs(double theta, int32_t s, orc_scheme* S)
+{
+    memset(S, 0, sizeof(*S));
+    S->s = s;
+    S->wkind = ORC_W_LOWER;
+    for (int r = 0; r < s; ++r) {
+        S->b[r] = 1.0;
+        for (int jj = 0; jj < r; ++jj) {
+            S->a[r * ORC_MAXS + jj] = theta;
+            S->q[r * ORC_MAXS + jj] = -1.0;
+        }
+    }
+    S->theta = theta;
+    S->nu = theta;
+}
+
+void orc_solve_lower(const orc_problem* P, const int32_t* levels, double thdt, const double* R, double* K)
+{
+    orc_grid G;
+    grid_make(&G, P, levels);
+    solve_lower(P, &G, thdt, R, K);
 }
 
 void orc_initial_data(const orc_problem* P, const int32_t* levels, double* Y)

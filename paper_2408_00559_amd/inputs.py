@@ -19,6 +19,8 @@ import numpy as np
 
 CAPLET = "caplet"
 SWAPTION = "swaption"
+NEUMANN = "neumann"
+DIRICHLET = "dirichlet"
 
 
 @dataclass
@@ -38,12 +40,15 @@ class Problem:
     K: float
     xeval: List[float]           # length d: (F_1(0), ..., V(0))
     discount: float = 1.0        # price = discount * u(T, xeval)
+    boundary: str = "neumann"    # upper faces of the rate axes: NEUMANN (eq. bound1) or DIRICHLET
+                                 # (the payoff, eq. bound1_0); V = V^max is Neumann in both
 
     def check(self) -> "Problem":
         n = self.d - 1
         assert len(self.alpha) == n and len(self.phi) == n and len(self.tau) == n
         assert len(self.rho) == n and all(len(r) == n for r in self.rho)
         assert len(self.xmax) == self.d and len(self.xeval) == self.d
+        assert self.boundary in (NEUMANN, DIRICHLET)
         return self
 
 
