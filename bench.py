@@ -45,10 +45,10 @@ def kernel_class_of(name: str):
         if sym in name:       # template arguments <T, D, OP[, R]>
             op = name.split(sym, 1)[1].split(">", 1)[0].split(",")[2].strip()
             return {"0": "operator", "1": "operator", "2": "stage1", "3": "stage2", "4": "refine"}[op]
-    for k in ("k_node", "k_unit_values", "k_combine", "k_resident"):
+    for k in ("k_node", "k_unit_values", "k_combine", "k_resident", "k_lincomb", "k_lower"):
         if k in name:
             return {"k_node": "init", "k_unit_values": "unit_values", "k_combine": "combine",
-                    "k_resident": "resident"}[k]
+                    "k_resident": "resident", "k_lincomb": "lincomb", "k_lower": "lower"}[k]
     assert L.K_NAMES
     return None
 

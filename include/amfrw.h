@@ -17,6 +17,8 @@
  *     paper), in the plan precision, axis 1 fastest: the element of unit u at multi-index j sits at
  *     unit_offset(u) + sum_i (j_i - 1) * prod_{k<i} M_k.  Lower-face (Outer) values are implied:
  *     the payoff for solution vectors, 0 for stage increments.  Axis d-1 is the volatility V.
+ *     With AMF_BC_DIRICHLET the nodes j_i = M_i of a rate axis are stored as well but are boundary
+ *     data: the solution holds the payoff there and stage increments hold 0.
  */
 #ifndef AMFRW_H
 #define AMFRW_H
@@ -28,7 +30,7 @@
 extern "C" {
 #endif
 
-#define AMF_ABI_VERSION 1
+#define AMF_ABI_VERSION 2
 #define AMF_MAX_D 8        /* descriptor capacity; kernels are built for d = 2..6 */
 #define AMF_MAX_STAGES 6
 
@@ -49,15 +51,32 @@ typedef enum {
     AMF_PAYOFF_SWAPTION = 1  /* max{ sum_i tau_i (F_i - K) / prod_{l<=i} (1 + tau_l F_l), 0 }   */
 } amf_payoff;
 
+/* Conditions on the upper faces F_i = F_i^max of the rate axes (Section 2).  The lower faces carry
+ * the payoff and V = V^max is homogeneous Neumann in both. */
+typedef enum {
+    AMF_BC_NEUMANN = 0,      /* homogeneous Neumann, eq (bound1): the paper's choice               */
+    AMF_BC_DIRICHLET = 1     /* the payoff, eq (bound1_0): the upper rate faces are boundary data,  */
+                             /* so a rate axis of M_i intervals has M_i - 1 unknowns               */
+} amf_boundary;
+
+/* Matrix W of the W-method (row-s). */
+typedef enum {
+    AMF_W_AMF = 0,           /* the AMF-refined W of eq (Wmat1): per stage the chain of directional */
+                             /* solves, the refinement and a second chain (eq amfrw)               */
+    AMF_W_LOWER = 1          /* W = P, the lower triangle (diagonal included) of the semi-discrete  */
+                             /* matrix in the theta_0 order: a fixed number of Gauss-Seidel sweeps  */
+                             /* of the theta-method written as a W-method (Section 4.2, eq (GS))    */
+} amf_w_matrix;
+
 /* One pricing instance: the data of the PDE (mmNd) in time-to-maturity form, with coefficients
- * (coef_diff), (coef_mix), (coef_adv), the domain of Section 3 and the boundary conditions (bound1):
- * Dirichlet payoff on the lower faces, homogeneous Neumann on the upper faces.  Copied at
- * amf_plan_create; the caller may free it afterwards. */
+ * (coef_diff), (coef_mix), (coef_adv), the domain of Section 3 and the boundary conditions: the
+ * payoff on the lower faces, homogeneous Neumann at V = V^max, and on the upper faces of the rate
+ * axes the kind `boundary` selects.  Copied at amf_plan_create; the caller may free it afterwards. */
 typedef struct {
     uint32_t struct_size;                       /* = sizeof(amf_problem)                          */
     int32_t d;                                  /* N: d-1 forward rates plus V, 2 <= d <= 6      */
     int32_t payoff;                             /* amf_payoff                                     */
-    int32_t reserved;
+    int32_t boundary;                           /* amf_boundary                                   */
     double beta;                                /* elasticity, 0 <= beta <= 1                     */
     double sigma;                               /* volatility of V (>= 0)                         */
     double alpha[AMF_MAX_D - 1];                /* alpha_i >= 0                                   */
@@ -71,8 +90,9 @@ typedef struct {
     double discount;                            /* price = discount * u(T, x_eval)                */
 } amf_problem;
 
-/* s-stage AMFR-W method: eq (row-s) with the W of eq (Wmat1), stages as eq (amfrw).  a and q are
- * stored row-major [r*AMF_MAX_STAGES + j] for j < r.  This build runs s = 2. */
+/* s-stage W-method, eq (row-s): (I - theta dt W) K_r = dt F(Y_n + sum_j a_rj K_j) + sum_j q_rj K_j,
+ * Y_{n+1} = Y_n + sum_r b_r K_r, with W chosen by w_matrix (stages as eq (amfrw) for the AMF W).
+ * a and q are stored row-major [r*AMF_MAX_STAGES + j] for j < r; 1 <= stages <= AMF_MAX_STAGES. */
 typedef struct {
     uint32_t struct_size;
     int32_t stages;
@@ -80,7 +100,9 @@ typedef struct {
     double q[AMF_MAX_STAGES * AMF_MAX_STAGES];
     double b[AMF_MAX_STAGES];
     double theta;
-    double nu;                                  /* AMF parameter of (Wmat1)                       */
+    double nu;                                  /* AMF parameter of (Wmat1) (AMF_W_AMF only)      */
+    int32_t w_matrix;                           /* amf_w_matrix                                   */
+    int32_t reserved;                           /* 0                                              */
 } amf_scheme;
 
 /* Either one full grid (M_i = 2^levels[i]) or the combination technique at level n with offset psi:
@@ -121,13 +143,19 @@ const char* amf_last_error(void);
  * third order; nu = theta (the paper leaves nu unprinted; nu = theta reproduces its tables). */
 amf_status amf_scheme_amfrw2(amf_scheme* out);
 
+/* The theta-method (thetamet) with `stages` Gauss-Seidel sweeps (GS) as a W-method (Section 4.2):
+ * W = P, a_rj = theta, q_rj = -1, b_r = 1; second order at theta = 1/2 for stages >= 2.
+ * AMF_E_INVALID unless 0 < theta <= 1 and 1 <= stages <= AMF_MAX_STAGES. */
+amf_status amf_scheme_theta_gs(double theta, int32_t stages, amf_scheme* out);
+
 /* Build a plan: enumerate the component grids of `grid` for each of the n_probs problems (all with
  * the same d), lay out the device workspace, tabulate the 1-D coefficient factors of (coef_diff),
  * (coef_mix), (coef_adv) in FP64 and round them once to the plan precision.  dt = maturity/n_steps
  * per problem.  richardson = 1 also runs 2*n_steps and combines prices as (8 P_fine - P_coarse)/7
- * (fourth order in time from the third-order scheme).  Errors: AMF_E_INVALID for out-of-range
- * descriptors (d, levels, n < d-1, psi, beta, correlations, x_eval outside the domain, steps < 1),
- * AMF_E_UNSUPPORTED for stages != 2. */
+ * (fourth order in time from a third-order scheme such as AMFR-W2).  Errors: AMF_E_INVALID for
+ * out-of-range descriptors (d, levels, n < d-1, psi, beta, correlations, boundary, x_eval outside
+ * the domain, steps < 1, stages, w_matrix, theta, nu), AMF_E_UNSUPPORTED for an axis-1 level above
+ * 10. */
 amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_grid_spec* grid,
                            const amf_scheme* scheme, amf_precision precision, int32_t n_steps,
                            int32_t richardson, amf_plan** out);
@@ -160,6 +188,12 @@ amf_status amf_solve(amf_plan* plan, void* stream);
  * enabling, binding or changing the schedule; kernels only, no memset or copy nodes) instead of
  * launching ~10 d kernels per step from the host.  Not used while per-kernel profiling is on. */
 amf_status amf_graph_enable(amf_plan* plan, int32_t on);
+
+/* amf_combine, then wait for the stream and check the prices: AMF_E_NUMERIC (message naming the
+ * first problem) when any price is not finite, the prices still written; AMF_OK otherwise.  For
+ * callers that want the paper's failure signal of an unstable configuration without reading the
+ * prices back themselves. */
+amf_status amf_combine_checked(amf_plan* plan, double* d_prices, void* stream);
 
 /* Per-unit value u_l(x_eval) by tensor-product linear interpolation (Section 5), in FP64, one per
  * unit in unit order, written to d_values (device, n_units doubles). */
@@ -239,7 +273,9 @@ typedef enum {
     AMF_K_UNIT_VALUES = 11,     /* interpolation at x_eval                                    */
     AMF_K_COMBINE = 12,         /* FP64 combination                                           */
     AMF_K_RESIDENT = 13,        /* unit-resident time loop (all stages and solves in LDS)     */
-    AMF_K_COUNT = 14
+    AMF_K_LINCOMB = 14,         /* stage combinations sum_j c_j K_j of schemes with s > 2     */
+    AMF_K_LOWER = 15,           /* (I - theta dt P) solves of the W = P method (wavefronts)   */
+    AMF_K_COUNT = 16
 } amf_kernel_class;
 
 typedef struct {
@@ -304,6 +340,25 @@ amf_status amf_mlp_backward(amf_mlp* mlp, const float* d_dy, int32_t batch, void
 amf_status amf_mlp_train_step(amf_mlp* mlp, const float* d_x, const float* d_target, int32_t batch,
                               float lr, float err_weight, float* d_loss, void* stream);
 void amf_mlp_destroy(amf_mlp* mlp);
+
+/* Router of the surrogate (form 4): the box the network was trained on (n_in lower and upper
+ * bounds, host arrays) and the calibration factor that scales its error estimate (Section "learned
+ * part" of the build: the estimate is multiplied by calib before it is compared with a tolerance). */
+amf_status amf_mlp_set_router(amf_mlp* mlp, const float* box_lo, const float* box_hi, float calib);
+
+/* Price the n_problems requests of `fallback` with the network where it is trusted, else with the
+ * solver.  d_x: [n, n_in] FP32 features on the device, row i describing problem i of the plan.
+ * Request i is served by the network when its features lie inside the router's box, the network
+ * price p_i is finite and its calibrated error estimate e_i = calib * est_i satisfies
+ * e_i <= tol or e_i |p_i| <= abs_floor (a relative tolerance with an absolute floor); every other
+ * request is routed to the solver: a plan of exactly those problems (same grid, scheme, precision,
+ * steps and schedule) is built on the host, bound into the fallback plan's own workspace, solved
+ * and combined (eq amfrw, eq modifiedCombTechnique).  Outputs (device): d_prices[n] FP64,
+ * d_used_solver[n] 0/1.  Synchronises the stream.  When any request was routed, the fallback
+ * plan's state is overwritten (its tables are uploaded again before returning): call amf_solve
+ * before reading its state.  AMF_E_NUMERIC when a final price is not finite. */
+amf_status amf_price_or_fallback(amf_mlp* mlp, amf_plan* fallback, const float* d_x, float tol,
+                                 float abs_floor, double* d_prices, int32_t* d_used_solver, void* stream);
 
 /* Release host resources.  Device memory stays owned by the caller.  NULL is allowed. */
 void amf_plan_destroy(amf_plan* plan);

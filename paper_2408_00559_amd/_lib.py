@@ -14,13 +14,15 @@ RHO_LD = MAX_D - 1
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_HIP, E_NUMERIC, E_STATE = range(7)
 FP64, FP32 = 0, 1
 PAYOFF_CAPLET, PAYOFF_SWAPTION = 0, 1
+BC_NEUMANN, BC_DIRICHLET = 0, 1
+W_AMF, W_LOWER = 0, 1
 STATUS_NAMES = {0: "AMF_OK", 1: "AMF_E_INVALID", 2: "AMF_E_UNSUPPORTED", 3: "AMF_E_NOMEM",
                 4: "AMF_E_HIP", 5: "AMF_E_NUMERIC", 6: "AMF_E_STATE"}
 
 
 class AmfProblem(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("d", C.c_int32), ("payoff", C.c_int32),
-                ("reserved", C.c_int32), ("beta", C.c_double), ("sigma", C.c_double),
+                ("boundary", C.c_int32), ("beta", C.c_double), ("sigma", C.c_double),
                 ("alpha", C.c_double * (MAX_D - 1)), ("phi", C.c_double * (MAX_D - 1)),
                 ("tau", C.c_double * (MAX_D - 1)), ("rho", C.c_double * (RHO_LD * RHO_LD)),
                 ("x_max", C.c_double * MAX_D), ("maturity", C.c_double), ("strike", C.c_double),
@@ -31,7 +33,7 @@ class AmfScheme(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("stages", C.c_int32),
                 ("a", C.c_double * (MAX_STAGES * MAX_STAGES)),
                 ("q", C.c_double * (MAX_STAGES * MAX_STAGES)), ("b", C.c_double * MAX_STAGES),
-                ("theta", C.c_double), ("nu", C.c_double)]
+                ("theta", C.c_double), ("nu", C.c_double), ("w_matrix", C.c_int32), ("reserved", C.c_int32)]
 
 
 class AmfGridSpec(C.Structure):
@@ -59,7 +61,7 @@ class AmfKernelStat(C.Structure):
 
 K_NAMES = ["init", "operator", "stage1", "stage2", "refine", "sweep_contig", "sweep_contig_long",
            "sweep_strided", "sweep_strided_long", "sweep_update", "sweep_update_long", "unit_values",
-           "combine", "resident"]
+           "combine", "resident", "lincomb", "lower"]
 # device kernel symbol of each class (template arguments omitted)
 K_SYMBOLS = {"init": "k_node", "operator": "k_stencil<OP_F_PAYOFF>", "stage1": "k_stencil_vec<OP_STAGE1, R, FUSE>",
              "stage2": "k_stencil_vec<OP_STAGE2, R, FUSE>", "refine": "k_stencil_vec<OP_REFINE, R, FUSE>",
@@ -68,7 +70,8 @@ K_SYMBOLS = {"init": "k_node", "operator": "k_stencil<OP_F_PAYOFF>", "stage1": "
              "sweep_strided_long": "k_sweep_strided_long<EPI_STORE, V>",
              "sweep_update": "k_sweep_strided<EPI_UPDATE>",
              "sweep_update_long": "k_sweep_strided_long<EPI_UPDATE, V>",
-             "unit_values": "k_unit_values", "combine": "k_combine", "resident": "k_resident"}
+             "unit_values": "k_unit_values", "combine": "k_combine", "resident": "k_resident",
+             "lincomb": "k_lincomb", "lower": "k_lower"}
 K_COUNT = len(K_NAMES)
 
 
@@ -94,6 +97,8 @@ def lib():
         L.amf_last_error.restype = C.c_char_p
         L.amf_scheme_amfrw2.restype = st
         L.amf_scheme_amfrw2.argtypes = [C.POINTER(AmfScheme)]
+        L.amf_scheme_theta_gs.restype = st
+        L.amf_scheme_theta_gs.argtypes = [C.c_double, C.c_int32, C.POINTER(AmfScheme)]
         L.amf_plan_create.restype = st
         L.amf_plan_create.argtypes = [C.POINTER(AmfProblem), C.c_int32, C.POINTER(AmfGridSpec),
                                       C.POINTER(AmfScheme), C.c_int32, C.c_int32, C.c_int32,
@@ -117,6 +122,8 @@ def lib():
         L.amf_unit_values.argtypes = [vp, vp, vp]
         L.amf_combine.restype = st
         L.amf_combine.argtypes = [vp, vp, vp]
+        L.amf_combine_checked.restype = st
+        L.amf_combine_checked.argtypes = [vp, vp, vp]
         L.amf_state_read.restype = st
         L.amf_state_read.argtypes = [vp, vp, vp]
         L.amf_apply_operator.restype = st
@@ -142,10 +149,12 @@ def check(status: int):
         raise AmfError(status, lib().amf_last_error().decode())
 
 
-EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_plan_create",
+EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_scheme_theta_gs", "amf_plan_create",
             "amf_plan_info_get", "amf_unit_info", "amf_plan_bind", "amf_init", "amf_time_step",
-            "amf_solve", "amf_graph_enable", "amf_unit_values", "amf_combine", "amf_state_read", "amf_apply_operator",
+            "amf_solve", "amf_graph_enable", "amf_unit_values", "amf_combine", "amf_combine_checked",
+            "amf_state_read", "amf_apply_operator",
             "amf_axis_solve", "amf_schedule_get", "amf_schedule_set", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy",
             "amf_mlp_last_error", "amf_mlp_create", "amf_mlp_info_get", "amf_mlp_bind",
             "amf_mlp_set_normalization", "amf_mlp_params", "amf_mlp_grads", "amf_mlp_forward",
-            "amf_mlp_backward", "amf_mlp_train_step", "amf_mlp_destroy"]
+            "amf_mlp_backward", "amf_mlp_train_step", "amf_mlp_destroy", "amf_mlp_set_router",
+            "amf_price_or_fallback"]

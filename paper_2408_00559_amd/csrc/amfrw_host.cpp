@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <new>
 #include <string>
 #include <thread>
@@ -35,12 +36,17 @@ constexpr int RHO_LD = AMF_MAX_D - 1;   // leading dimension of amf_problem::rho
 
 }  // namespace
 
-// Grid vectors: the solution W = Y - g, the first stage K1, two work vectors and F(g).
-enum VecId { V_W = 0, V_K1 = 1, V_A = 2, V_B = 3, V_G = 4, N_VEC = 5 };
+// Grid vectors: the solution W = Y - g, two work vectors, F(g), then the stages K_1 .. K_{s-1} of
+// the scheme, and for s > 2 two combination vectors (sum_j a_rj K_j, sum_j q_rj K_j).
+enum VecId { V_W = 0, V_A = 1, V_B = 2, V_G = 3, V_K0 = 4 };
+constexpr int MAX_VEC = V_K0 + AMF_MAX_STAGES - 1 + 2;
 
 struct amf_plan {
     int d = 0, prec = 0, steps = 0, richardson = 0, n_probs = 0, n_units = 0;
     amf_scheme sch{};
+    amf_grid_spec grid{};
+    int n_vec = 0;                         // grid vectors in the workspace
+    int v_z = -1, v_q = -1;                // combination vectors (s > 2)
     std::vector<amf_problem> probs;
     std::vector<UnitDev> units;            // n_units + sentinel
     std::vector<double> coef;              // combination coefficient per unit
@@ -62,10 +68,17 @@ struct amf_plan {
     int64_t total = 0;                     // elements per grid vector (with alignment padding)
     int64_t inner = 0;                     // inner points over all units
 
-    size_t off_vec[N_VEC]{}, off_units = 0, off_probs = 0, off_tab = 0, off_fac = 0, off_blk = 0;
+    // W = P solves: hyperplanes of axis-0 lines per unit (built only for w_matrix = AMF_W_LOWER)
+    std::vector<int32_t> gs_unit_plane0, gs_lines;
+    std::vector<int64_t> gs_plane_line0;
+    size_t off_gsu = 0, off_gsp = 0, off_gsl = 0;
+
+    size_t off_vec[MAX_VEC]{}, off_units = 0, off_probs = 0, off_tab = 0, off_fac = 0, off_blk = 0;
     size_t off_blkr[4]{};
     size_t off_axu[MAXD]{}, off_axl[MAXD]{}, off_axb[MAXD]{};
-    size_t off_coef = 0, off_vals = 0, off_valsc = 0, ws_bytes = 0;
+    size_t off_coef = 0, off_vals = 0, off_valsc = 0, off_flag = 0;
+    size_t core_bytes = 0;                 // everything but the fallback staging area
+    size_t off_fb = 0, ws_bytes = 0;       // staging of routed prices and their indices
     size_t elem = 8;
 
     char* ws = nullptr;
@@ -147,6 +160,8 @@ amf_status validate_problem(const amf_problem& p, int d, int idx)
     if (p.d != d) return fail(AMF_E_INVALID, "all problems must share d" + at);
     if (p.payoff != AMF_PAYOFF_CAPLET && p.payoff != AMF_PAYOFF_SWAPTION)
         return fail(AMF_E_INVALID, "unknown payoff" + at);
+    if (p.boundary != AMF_BC_NEUMANN && p.boundary != AMF_BC_DIRICHLET)
+        return fail(AMF_E_INVALID, "unknown boundary kind" + at);
     if (!(p.beta >= 0.0 && p.beta <= 1.0)) return fail(AMF_E_INVALID, "beta must lie in [0,1]" + at);
     if (!(p.sigma >= 0.0) || !std::isfinite(p.sigma)) return fail(AMF_E_INVALID, "sigma must be >= 0" + at);
     if (!(p.maturity > 0.0) || !std::isfinite(p.maturity)) return fail(AMF_E_INVALID, "maturity must be > 0" + at);
@@ -201,14 +216,15 @@ void append_axis_table(std::vector<double>& t, const amf_problem& p, int axis, i
 
 // Thomas factors of (I - nu dt A_axis) along one line (Lemma lema:ls) from the FP64 diagonal
 // weights delta_r = d_axis/h^2: appends inv_r = 1/pivot_r, a_r inv_r, c'_r (three blocks of M).
-void append_factors(std::vector<double>& f, const std::vector<double>& delta, double nudt)
+// dir: the last node is a Dirichlet face (eq bound1_0), whose row is the identity.
+void append_factors(std::vector<double>& f, const std::vector<double>& delta, double nudt, bool dir)
 {
     const int M = (int)delta.size();
     const size_t b = f.size();
     f.resize(b + 3 * (size_t)M);
     double cprev = 0.0;
     for (int r = 0; r < M; ++r) {
-        const double nd = nudt * delta[r];
+        const double nd = (dir && r == M - 1) ? 0.0 : nudt * delta[r];
         const double bb = 1.0 + 2.0 * nd;
         const double a = (r == 0) ? 0.0 : ((r == M - 1) ? -2.0 * nd : -nd);
         const double c = (r == M - 1) ? 0.0 : -nd;
@@ -257,6 +273,28 @@ amf_status amf_scheme_amfrw2(amf_scheme* out)
     out->b[1] = 3.0 / 4.0;
     out->theta = (3.0 + std::sqrt(3.0)) / 6.0;
     out->nu = out->theta;
+    out->w_matrix = AMF_W_AMF;
+    return AMF_OK;
+}
+
+amf_status amf_scheme_theta_gs(double theta, int32_t stages, amf_scheme* out)
+{
+    if (!out) return fail(AMF_E_INVALID, "null scheme");
+    if (!(theta > 0.0 && theta <= 1.0)) return fail(AMF_E_INVALID, "theta must lie in (0, 1]");
+    if (stages < 1 || stages > AMF_MAX_STAGES) return fail(AMF_E_INVALID, "stages must lie in [1, 6]");
+    std::memset(out, 0, sizeof(*out));
+    out->struct_size = sizeof(amf_scheme);
+    out->stages = stages;
+    for (int r = 0; r < stages; ++r) {
+        out->b[r] = 1.0;
+        for (int j = 0; j < r; ++j) {
+            out->a[r * AMF_MAX_STAGES + j] = theta;
+            out->q[r * AMF_MAX_STAGES + j] = -1.0;
+        }
+    }
+    out->theta = theta;
+    out->nu = theta;
+    out->w_matrix = AMF_W_LOWER;
     return AMF_OK;
 }
 
@@ -273,8 +311,17 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
     if (precision != AMF_FP64 && precision != AMF_FP32) return fail(AMF_E_INVALID, "unknown precision");
     if (n_steps < 1) return fail(AMF_E_INVALID, "n_steps must be >= 1");
     if (richardson != 0 && richardson != 1) return fail(AMF_E_INVALID, "richardson must be 0 or 1");
-    if (scheme->stages != 2) return fail(AMF_E_UNSUPPORTED, "only 2-stage AMFR-W schemes are built");
-    if (!(scheme->theta > 0.0) || !(scheme->nu > 0.0)) return fail(AMF_E_INVALID, "theta and nu must be > 0");
+    if (scheme->stages < 1 || scheme->stages > AMF_MAX_STAGES) return fail(AMF_E_INVALID, "stages must lie in [1, 6]");
+    if (scheme->w_matrix != AMF_W_AMF && scheme->w_matrix != AMF_W_LOWER) return fail(AMF_E_INVALID, "unknown w_matrix");
+    if (!(scheme->theta > 0.0) || !std::isfinite(scheme->theta)) return fail(AMF_E_INVALID, "theta must be > 0");
+    if (scheme->w_matrix == AMF_W_AMF && (!(scheme->nu > 0.0) || !std::isfinite(scheme->nu)))
+        return fail(AMF_E_INVALID, "nu must be > 0");
+    for (int r = 0; r < scheme->stages; ++r) {
+        if (!std::isfinite(scheme->b[r])) return fail(AMF_E_INVALID, "scheme coefficients must be finite");
+        for (int j = 0; j < r; ++j)
+            if (!std::isfinite(scheme->a[r * AMF_MAX_STAGES + j]) || !std::isfinite(scheme->q[r * AMF_MAX_STAGES + j]))
+                return fail(AMF_E_INVALID, "scheme coefficients must be finite");
+    }
     const int d = probs[0].d;
     if (d < 2 || d > MAXD) return fail(AMF_E_INVALID, "d must lie in [2, 6]");
     for (int p = 0; p < n_probs; ++p) {
@@ -314,7 +361,16 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->richardson = richardson;
         P->n_probs = n_probs;
         P->sch = *scheme;
+        P->grid = *grid;
         P->probs.assign(probs, probs + n_probs);
+        {
+            const int S = scheme->stages;
+            P->n_vec = V_K0 + (S - 1);
+            if (S > 2) {
+                P->v_z = P->n_vec++;
+                P->v_q = P->n_vec++;
+            }
+        }
         const int ng = (int)glv.size();
         const int64_t nu64 = (int64_t)ng * n_probs;
         if (nu64 > (int64_t)1 << 30) {
@@ -345,6 +401,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             pd.K = pr.strike;
             pd.discount = pr.discount;
             pd.payoff = pr.payoff;
+            pd.dirichlet = pr.boundary == AMF_BC_DIRICHLET ? 1 : 0;
             pd.cst = 0;
             pd.unit_begin = p * ng;
             pd.unit_end = (p + 1) * ng;
@@ -402,7 +459,8 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                         for (int run = 0; run < 2; ++run) {
                             const double h = run == 0 ? pr.maturity / (double)n_steps : 0.5 * pr.maturity / (double)n_steps;
                             for (int jv = 0; jv < nlines; ++jv)
-                                append_factors(T.fac[run], delta_of(i, L, LV, jv, t, tv), scheme->nu * h);
+                                append_factors(T.fac[run], delta_of(i, L, LV, jv, t, tv), scheme->nu * h,
+                                               pr.boundary == AMF_BC_DIRICHLET && i < d - 1);
                         }
                     }
                     T.unit_fac[(size_t)g * d + i] = fac_of[i][key];
@@ -504,7 +562,8 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->max_m0 = max_m0;
         int max_lsum = 0;
         for (int u = 0; u < P->n_units; ++u) max_lsum = std::max(max_lsum, (int)P->units[u].lsum);
-        P->res_ok = max_lsum <= (precision == AMF_FP64 ? RES_MAX_LSUM_F64 : RES_MAX_LSUM_F32);
+        P->res_ok = max_lsum <= (precision == AMF_FP64 ? RES_MAX_LSUM_F64 : RES_MAX_LSUM_F32) &&
+                    scheme->stages == 2 && scheme->w_matrix == AMF_W_AMF;
         P->res_lds_len = (1 << max_lsum) + ((1 << max_lsum) >> 4);
         const int rmax = precision == AMF_FP64 ? STENCIL_R_F64 : STENCIL_R_F32;
         P->stencil_r = std::min(rmax, min_m0) >= 4 ? 4 : (std::min(rmax, min_m0) >= 2 ? 2 : 1);
@@ -608,10 +667,46 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                 if (e) std::rethrow_exception(e);
         }
 
+        // W = P: per unit, its axis-0 lines bucketed by the hyperplane h = sum_{i>=1} i (j_i - 1)
+        if (scheme->w_matrix == AMF_W_LOWER) {
+            P->gs_unit_plane0.assign((size_t)P->n_units + 1, 0);
+            P->gs_plane_line0.push_back(0);
+            std::vector<int32_t> hp, cnt, at;
+            for (int u = 0; u < P->n_units; ++u) {
+                const UnitDev& U = P->units[u];
+                const int nl = 1 << (U.lsum - U.lv[0]);
+                int planes = 1;
+                for (int i = 1; i < d; ++i) planes += i * ((1 << U.lv[i]) - 1);
+                hp.assign((size_t)nl, 0);
+                cnt.assign((size_t)planes, 0);
+                for (int l = 0; l < nl; ++l) {
+                    int h = 0, sh = 0;
+                    for (int i = 1; i < d; ++i) {
+                        h += i * ((l >> sh) & ((1 << U.lv[i]) - 1));
+                        sh += U.lv[i];
+                    }
+                    hp[(size_t)l] = h;
+                    ++cnt[(size_t)h];
+                }
+                at.assign((size_t)planes, 0);
+                const int64_t base = (int64_t)P->gs_lines.size();
+                int64_t run = base;
+                for (int h = 0; h < planes; ++h) {
+                    at[(size_t)h] = (int32_t)(run - base);
+                    run += cnt[(size_t)h];
+                    P->gs_plane_line0.push_back(run);
+                }
+                P->gs_lines.resize((size_t)run);
+                for (int l = 0; l < nl; ++l) P->gs_lines[(size_t)(base + at[(size_t)hp[(size_t)l]]++)] = l;
+                P->gs_unit_plane0[(size_t)u + 1] = P->gs_unit_plane0[(size_t)u] + planes;
+                if ((int64_t)P->gs_unit_plane0[(size_t)u + 1] > INT32_MAX / 2) throw std::bad_alloc();
+            }
+        }
+
         // workspace layout
         size_t o = 0;
         const size_t vb = align_up((size_t)P->total * P->elem, 256);
-        for (int v = 0; v < N_VEC; ++v) {
+        for (int v = 0; v < P->n_vec; ++v) {
             P->off_vec[v] = o;
             o += vb;
         }
@@ -631,9 +726,15 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             P->off_axl[ax] = take(P->ax_line_off[ax].size() * sizeof(int64_t));
             P->off_axb[ax] = take(P->ax_blk[ax].size() * sizeof(SweepBlk));
         }
+        P->off_gsu = take(P->gs_unit_plane0.size() * sizeof(int32_t));
+        P->off_gsp = take(P->gs_plane_line0.size() * sizeof(int64_t));
+        P->off_gsl = take(P->gs_lines.size() * sizeof(int32_t));
         P->off_coef = take(P->coef.size() * sizeof(double));
         P->off_vals = take((size_t)P->n_units * sizeof(double));
         P->off_valsc = take((size_t)P->n_units * sizeof(double));
+        P->off_flag = take(sizeof(int32_t));
+        P->core_bytes = o;
+        P->off_fb = take((size_t)n_probs * (sizeof(double) + sizeof(int32_t)));
         P->ws_bytes = o;
     } catch (const std::bad_alloc&) {
         delete P;
@@ -674,13 +775,14 @@ amf_status amf_unit_info(const amf_plan* P, int64_t unit, int32_t* problem, int3
     return AMF_OK;
 }
 
-amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
+}  // extern "C"
+
+namespace {
+
+// Upload the plan's tables into device memory at d_ws (at least core_bytes; 256-byte aligned) and
+// point the device view there.  Synchronises the stream.
+amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
 {
-    if (!P) return fail(AMF_E_INVALID, "null plan");
-    if (!d_ws) return fail(AMF_E_INVALID, "null workspace");
-    if (bytes < P->ws_bytes) return fail(AMF_E_INVALID, "workspace too small: need " + std::to_string(P->ws_bytes) + " bytes");
-    if (((uintptr_t)d_ws & 255u) != 0) return fail(AMF_E_INVALID, "workspace must be 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
     P->drop_graph();
     P->ws = (char*)d_ws;
     P->bound = false;
@@ -711,6 +813,9 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
         if ((st = upload(P->ws + P->off_axl[ax], P->ax_line_off[ax].data(), P->ax_line_off[ax].size() * 8, s))) return st;
         if ((st = upload(P->ws + P->off_axb[ax], P->ax_blk[ax].data(), P->ax_blk[ax].size() * sizeof(SweepBlk), s))) return st;
     }
+    if ((st = upload(P->ws + P->off_gsu, P->gs_unit_plane0.data(), P->gs_unit_plane0.size() * 4, s))) return st;
+    if ((st = upload(P->ws + P->off_gsp, P->gs_plane_line0.data(), P->gs_plane_line0.size() * 8, s))) return st;
+    if ((st = upload(P->ws + P->off_gsl, P->gs_lines.data(), P->gs_lines.size() * 4, s))) return st;
     if ((st = upload(P->ws + P->off_coef, P->coef.data(), P->coef.size() * 8, s))) return st;
     hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -744,8 +849,25 @@ amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
         D.ax_nblk_short[ax] = ns;
         D.ax_vec[ax] = P->ax_vec[ax];
     }
+    const bool gs = !P->gs_lines.empty();
+    D.gs_unit_plane0 = gs ? (const int32_t*)(P->ws + P->off_gsu) : nullptr;
+    D.gs_plane_line0 = gs ? (const int64_t*)(P->ws + P->off_gsp) : nullptr;
+    D.gs_lines = gs ? (const int32_t*)(P->ws + P->off_gsl) : nullptr;
     P->bound = true;
     return AMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amf_status amf_plan_bind(amf_plan* P, void* d_ws, uint64_t bytes, void* stream)
+{
+    if (!P) return fail(AMF_E_INVALID, "null plan");
+    if (!d_ws) return fail(AMF_E_INVALID, "null workspace");
+    if (bytes < P->ws_bytes) return fail(AMF_E_INVALID, "workspace too small: need " + std::to_string(P->ws_bytes) + " bytes");
+    if (((uintptr_t)d_ws & 255u) != 0) return fail(AMF_E_INVALID, "workspace must be 256-byte aligned");
+    return bind_impl(P, d_ws, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -862,81 +984,153 @@ amf_status advance(amf_plan* P, int run, int n, hipStream_t s)
     return AMF_OK;
 }
 
-// One AMFR-W step (eq amfrw) of the 2-stage scheme on every unit.  run selects dt (0: coarse,
-// 1: fine half step of the Richardson pair).
+// out = (acc ? out : 0) + sum_j c[j] in[j] over whole grid vectors.
+hipError_t run_lincomb(amf_plan* P, void* out, bool acc, const void* const* in, const double* c, int n,
+                       hipStream_t s)
+{
+    LinArgs a{};
+    a.n = n;
+    a.acc = acc ? 1 : 0;
+    a.out = out;
+    for (int j = 0; j < n; ++j) {
+        a.in[j] = in[j];
+        a.c[j] = c[j];
+    }
+    return timed(P, AMF_K_LINCOMB, (n + 1 + (acc ? 1 : 0)) * P->vbytes(), s,
+                 [&] { return launch_lincomb(P->dev, P->prec, a, s); });
+}
+
+// One step of the s-stage W-method (row-s) on every unit; run selects dt (0: coarse, 1: fine half
+// step of the Richardson pair).  Stage r: the right-hand side dt F(Y + sum_j a_rj K_j) + sum_j q_rj K_j
+// (one operator launch; for r >= 2 the two sums are formed first), then either the AMF stage of
+// eq (amfrw) (chain of directional solves, refinement, second chain) or, for W = P, one
+// lower-triangular solve.  The update Y += sum_r b_r K_r is fused into the last directional solve
+// (AMF) or is one combination launch (W = P).
 amf_status one_step(amf_plan* P, int run, hipStream_t s)
 {
-    const int d = P->d;
+    const int d = P->d, S = P->sch.stages;
+    const bool lower = P->sch.w_matrix == AMF_W_LOWER;
     const int sel_dt = CST_RUN + 3 * run, sel_th = sel_dt + 2;
-    void *Wv = P->vec(V_W), *K1 = P->vec(V_K1), *A = P->vec(V_A), *B = P->vec(V_B), *G = P->vec(V_G);
-    const double a21 = P->sch.a[1 * AMF_MAX_STAGES + 0], q21 = P->sch.q[1 * AMF_MAX_STAGES + 0];
-    const bool fuse = P->fuse0 != 0;
+    void *Wv = P->vec(V_W), *A = P->vec(V_A), *B = P->vec(V_B), *G = P->vec(V_G);
+    auto K = [&](int r) { return P->vec(V_K0 + r); };
+    auto ca = [&](int r, int j) { return P->sch.a[r * AMF_MAX_STAGES + j]; };
+    auto cq = [&](int r, int j) { return P->sch.q[r * AMF_MAX_STAGES + j]; };
+    const bool fuse = P->fuse0 != 0 && !lower;
+    const int first = fuse ? 1 : 0;
     hipError_t e;
     // (I - nu dt A_1) .. (I - nu dt A_d) applied in axis order from axis `first` (1 when the operator
-    // launch already solved axis 0); the first solve reads `in`, the others work in place on `dst`
-    auto chain = [&](const void* in, void* dst, bool last_update, int first) -> hipError_t {
+    // launch already solved axis 0); the first solve reads `in`, the others work in place on `dst`;
+    // with `update` the last solve ends in W += b1 U + b2 x
+    auto chain = [&](const void* in, void* dst, bool update, const void* U, double b1, double b2) -> hipError_t {
         for (int ax = first; ax < d; ++ax) {
             SweepArgs a{};
             a.in = ax == first ? in : dst;
             a.out = dst;
             a.run = run;
             int epi = EPI_STORE;
-            if (last_update && ax == d - 1) {
+            if (update && ax == d - 1) {
                 epi = EPI_UPDATE;
                 a.out = Wv;
-                a.K1 = K1;
-                a.b1 = P->sch.b[0];
-                a.b2 = P->sch.b[1];
+                a.K1 = U;
+                a.b1 = b1;
+                a.b2 = b2;
             }
             hipError_t err = run_sweep(P, ax, epi, a, s);
             if (err != hipSuccess) return err;
         }
         return hipSuccess;
     };
-    const int first = fuse ? 1 : 0;
-    // ---- stage 1: K^(0) = dt F(Y) = dt (F0(W) + F(g)) -> A (and its axis-0 solve -> B)
-    StencilArgs st{};
-    st.X0 = Wv;
-    st.cG = G;
-    st.W = A;
-    st.S = fuse ? B : nullptr;
-    st.run = run;
-    st.scale_sel = sel_dt;
-    if ((e = run_stencil(P, OP_STAGE1, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    if ((e = chain(fuse ? B : A, B, false, first)) != hipSuccess) return hip_fail(e, "sweep");
-    // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d)) -> A (fused: its axis-0 solve -> K1)
-    st = StencilArgs{};
-    st.X0 = B;
-    st.W = A;
-    st.S = fuse ? K1 : nullptr;
-    st.run = run;
-    st.scale_sel = sel_th;
-    if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    if ((e = chain(fuse ? K1 : A, K1, false, first)) != hipSuccess) return hip_fail(e, "sweep");
-    // ---- stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1 -> A (and its axis-0 solve -> B)
-    st = StencilArgs{};
-    st.X0 = Wv;
-    st.X1 = K1;
-    st.cG = G;
-    st.W = A;
-    st.S = fuse ? B : nullptr;
-    st.run = run;
-    st.a = a21;
-    st.q = q21;
-    st.scale_sel = sel_dt;
-    if ((e = run_stencil(P, OP_STAGE2, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    if ((e = chain(fuse ? B : A, B, false, first)) != hipSuccess) return hip_fail(e, "sweep");
-    // fused: the refinement reads K^(0) (A) and K^(d) (B, with halo) and writes its axis-0 solve
-    // over A, which no other block reads
-    st = StencilArgs{};
-    st.X0 = B;
-    st.W = A;
-    st.S = fuse ? A : nullptr;
-    st.run = run;
-    st.scale_sel = sel_th;
-    if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
-    // second chain of stage 2 ends in W += b1 K1 + b2 K2
-    if ((e = chain(A, fuse ? A : B, true, first)) != hipSuccess) return hip_fail(e, "sweep");
+    for (int r = 0; r < S; ++r) {
+        const bool last = r == S - 1;
+        // ---- right-hand side K^(0) -> A (fused: and its axis-0 solve -> B)
+        StencilArgs st{};
+        st.X0 = Wv;
+        st.cG = G;
+        st.W = A;
+        st.S = fuse ? B : nullptr;
+        st.run = run;
+        st.scale_sel = sel_dt;
+        int op = OP_STAGE1;
+        if (r == 1) {
+            op = OP_STAGE2;
+            st.X1 = K(0);
+            st.X2 = K(0);
+            st.a = ca(1, 0);
+            st.q = cq(1, 0);
+        } else if (r >= 2) {
+            const void* in[AMF_MAX_STAGES];
+            double c[AMF_MAX_STAGES];
+            for (int j = 0; j < r; ++j) {
+                in[j] = K(j);
+                c[j] = ca(r, j);
+            }
+            if ((e = run_lincomb(P, P->vec(P->v_z), false, in, c, r, s)) != hipSuccess) return hip_fail(e, "lincomb");
+            for (int j = 0; j < r; ++j) c[j] = cq(r, j);
+            if ((e = run_lincomb(P, P->vec(P->v_q), false, in, c, r, s)) != hipSuccess) return hip_fail(e, "lincomb");
+            op = OP_STAGE2;
+            st.X1 = P->vec(P->v_z);
+            st.X2 = P->vec(P->v_q);
+            st.a = 1.0;
+            st.q = 1.0;
+        }
+        if ((e = run_stencil(P, op, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+        if (lower) {
+            // (I - theta dt P) K_r = K^(0); the last stage's K stays in A
+            LowerArgs la{};
+            la.rhs = A;
+            la.x = last ? A : K(r);
+            la.run = run;
+            e = timed(P, AMF_K_LOWER, 2.0 * P->vbytes(), s, [&] { return launch_lower(P->dev, P->prec, la, s); });
+            if (e != hipSuccess) return hip_fail(e, "lower solve");
+            if (last) {
+                const void* in[AMF_MAX_STAGES];
+                double c[AMF_MAX_STAGES];
+                for (int j = 0; j < S - 1; ++j) {
+                    in[j] = K(j);
+                    c[j] = P->sch.b[j];
+                }
+                in[S - 1] = A;
+                c[S - 1] = P->sch.b[S - 1];
+                if ((e = run_lincomb(P, Wv, true, in, c, S, s)) != hipSuccess) return hip_fail(e, "lincomb");
+            }
+            continue;
+        }
+        if ((e = chain(fuse ? B : A, B, false, nullptr, 0.0, 0.0)) != hipSuccess) return hip_fail(e, "sweep");
+        // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d)) -> A; fused: its axis-0 solve -> dst (the last
+        // stage's goes back over A, which no other block reads)
+        void* dst = last ? (fuse ? A : B) : K(r);
+        st = StencilArgs{};
+        st.X0 = B;
+        st.W = A;
+        st.S = fuse ? (last ? A : dst) : nullptr;
+        st.run = run;
+        st.scale_sel = sel_th;
+        if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
+        if (!last) {
+            if ((e = chain(fuse ? dst : A, dst, false, nullptr, 0.0, 0.0)) != hipSuccess) return hip_fail(e, "sweep");
+            continue;
+        }
+        // the last chain ends in W += sum_{j<s} b_j K_j + b_s K_s: for s = 2 the sum is b_1 K_1
+        const void* U = nullptr;
+        double b1 = 0.0;
+        if (S == 2) {
+            U = K(0);
+            b1 = P->sch.b[0];
+        } else if (S > 2) {
+            const void* in[AMF_MAX_STAGES];
+            double c[AMF_MAX_STAGES];
+            for (int j = 0; j < S - 1; ++j) {
+                in[j] = K(j);
+                c[j] = P->sch.b[j];
+            }
+            if ((e = run_lincomb(P, P->vec(P->v_z), false, in, c, S - 1, s)) != hipSuccess) return hip_fail(e, "lincomb");
+            U = P->vec(P->v_z);
+            b1 = 1.0;
+        } else {
+            U = G;              // s = 1: nothing to add (b1 = 0); any vector of the plan is a valid read
+        }
+        if ((e = chain(A, dst, true, U, b1, P->sch.b[S - 1])) != hipSuccess) return hip_fail(e, "sweep");
+    }
     return AMF_OK;
 }
 
@@ -961,6 +1155,8 @@ amf_status amf_time_step(amf_plan* P, int32_t n, void* stream)
     if (st) return st;
     if (!P->initialised) return fail(AMF_E_STATE, "amf_init has not been called");
     if (n < 0) return fail(AMF_E_INVALID, "n must be >= 0");
+    // the state no longer belongs to a completed Richardson pair: combine without extrapolation
+    P->have_coarse = false;
     return advance(P, 0, n, (hipStream_t)stream);
 }
 
@@ -1064,6 +1260,79 @@ amf_status amf_combine(amf_plan* P, double* d_prices, void* stream)
     return AMF_OK;
 }
 
+amf_status amf_combine_checked(amf_plan* P, double* d_prices, void* stream)
+{
+    amf_status st = amf_combine(P, d_prices, stream);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int32_t* flag = (int32_t*)(P->ws + P->off_flag);
+    hipError_t e = launch_first_nonfinite(d_prices, P->n_probs, flag, s);
+    if (e != hipSuccess) return hip_fail(e, "check prices");
+    int32_t bad = -1;
+    if ((e = hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (bad >= 0) return fail(AMF_E_NUMERIC, "non-finite price of problem " + std::to_string(bad) +
+                                              " (an unstable configuration: raise nu or the step count)");
+    return AMF_OK;
+}
+
+amf_status amf_price_or_fallback(amf_mlp* mlp, amf_plan* P, const float* d_x, float tol, float abs_floor,
+                                 double* d_prices, int32_t* d_used_solver, void* stream)
+{
+    amf_status st = check_bound(P);
+    if (st) return st;
+    if (!mlp || !d_x || !d_prices || !d_used_solver) return fail(AMF_E_INVALID, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int n = P->n_probs;
+    // 1. network prices and routing flags on the device
+    if ((st = mlp_route(mlp, d_x, n, tol, abs_floor, d_prices, d_used_solver, s))) return fail(st, mlp_error());
+    std::vector<int32_t> used((size_t)n), idx;
+    hipError_t e = hipMemcpyAsync(used.data(), d_used_solver, (size_t)n * 4, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (int i = 0; i < n; ++i)
+        if (used[(size_t)i]) idx.push_back(i);
+    const int k = (int)idx.size();
+    // 2. the routed requests through the solver
+    if (k == n) {
+        if ((st = amf_solve(P, stream)) || (st = amf_combine(P, d_prices, stream))) return st;
+    } else if (k > 0) {
+        std::vector<amf_problem> sub((size_t)k);
+        for (int j = 0; j < k; ++j) sub[(size_t)j] = P->probs[(size_t)idx[(size_t)j]];
+        amf_plan* Q = nullptr;
+        if ((st = amf_plan_create(sub.data(), k, &P->grid, &P->sch, (amf_precision)P->prec, P->steps,
+                                  P->richardson, &Q)))
+            return st;
+        std::unique_ptr<amf_plan> hold(Q);
+        // a subset of the parent's units packs into no more space than the parent's own layout
+        if (Q->core_bytes > P->core_bytes) return fail(AMF_E_STATE, "fallback plan does not fit the workspace");
+        Q->stencil_r = P->stencil_r;          // same grids per problem: the parent's schedule is valid
+        Q->xcd = P->xcd;
+        Q->fuse0 = P->fuse0;
+        Q->resident = P->resident && Q->res_ok;
+        double* stage = (double*)(P->ws + P->off_fb);
+        int32_t* sidx = (int32_t*)(P->ws + P->off_fb + (size_t)n * sizeof(double));
+        st = bind_impl(Q, P->ws, s);           // overwrites the parent's tables and state
+        if (!st) st = amf_solve(Q, stream);
+        if (!st) st = amf_combine(Q, stage, stream);
+        if (!st) st = upload(sidx, idx.data(), (size_t)k * 4, s);
+        if (!st && (e = launch_scatter(stage, sidx, k, d_prices, s)) != hipSuccess) st = hip_fail(e, "scatter");
+        if (!st && (e = hipStreamSynchronize(s)) != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+        // the parent's tables back in place (its state is gone: amf_solve before reading it)
+        amf_status st2 = bind_impl(P, P->ws, s);
+        if (st) return st;
+        if (st2) return st2;
+    }
+    // 3. the failure signal of an unstable configuration
+    int32_t* flag = (int32_t*)(P->ws + P->off_flag);
+    if ((e = launch_first_nonfinite(d_prices, n, flag, s)) != hipSuccess) return hip_fail(e, "check prices");
+    int32_t bad = -1;
+    if ((e = hipMemcpyAsync(&bad, flag, sizeof(bad), hipMemcpyDeviceToHost, s)) != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (bad >= 0) return fail(AMF_E_NUMERIC, "non-finite price of request " + std::to_string(bad));
+    return AMF_OK;
+}
+
 amf_status amf_state_read(amf_plan* P, void* d_out, void* stream)
 {
     amf_status st = check_bound(P);
@@ -1131,6 +1400,8 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (sc->resident != 0 && sc->resident != 1) return fail(AMF_E_INVALID, "resident must be 0 or 1");
     if (sc->resident && !P->res_ok) return fail(AMF_E_INVALID, "a unit exceeds the unit-resident size limit");
     if (sc->fuse_axis0 != 0 && sc->fuse_axis0 != 1) return fail(AMF_E_INVALID, "fuse_axis0 must be 0 or 1");
+    if (sc->fuse_axis0 && P->sch.w_matrix != AMF_W_AMF)
+        return fail(AMF_E_INVALID, "fuse_axis0 applies to the AMF W only");
     if (sc->fuse_axis0 && (r < 2 || NODE_BLOCK * r < P->max_m0))
         return fail(AMF_E_INVALID, "fuse_axis0 needs stencil_nodes >= 2 and 256 * stencil_nodes >= the longest axis-1 line");
     if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident || sc->fuse_axis0 != P->fuse0)

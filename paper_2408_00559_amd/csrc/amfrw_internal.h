@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "amfrw.h"
+
 namespace amf {
 
 constexpr int MAXD = 6;            // kernels are instantiated for d = 2..6
@@ -73,7 +75,13 @@ struct alignas(16) ProbDev {
     int32_t cst;          // offset of the CstIndex block in the table array
     int32_t unit_begin;   // units of this problem are [unit_begin, unit_end)
     int32_t unit_end;
+    int32_t dirichlet;    // 1: the upper faces of the rate axes hold the payoff (eq bound1_0)
+    int32_t pad_[3];
 };
+
+// Whether a node with rate-axis index j on an axis of M intervals is boundary data: the upper face
+// of a rate axis under the Dirichlet conditions of eq (bound1_0).
+__host__ __device__ __forceinline__ bool dir_face(int dirichlet, int j, int M) { return dirichlet && j == M; }
 
 // A block of the sweep along one axis: lines [line_start, line_end) of the axis' line list, all
 // of length 2^lm; k_start indexes the axis' unit list at line_start; vec: adjacent lines per
@@ -110,6 +118,11 @@ struct DevPlan {
     int64_t ax_nblk[MAXD];
     int64_t ax_nblk_short[MAXD];       // leading blocks with lm <= SHORT_LM
     int ax_vec[MAXD];                  // long strided lines: 16-byte vectors of adjacent lines per slot
+    // W = P solves: unit u's hyperplanes are [gs_unit_plane0[u], gs_unit_plane0[u+1]); plane p holds
+    // the axis-0 lines gs_lines[gs_plane_line0[p] .. gs_plane_line0[p+1]) (line id = loc >> lv_0)
+    const int32_t* gs_unit_plane0;
+    const int64_t* gs_plane_line0;
+    const int32_t* gs_lines;
 };
 
 // Stencil operation selector.  Solution vectors are stored as W = Y - g (zero on every lower face);
@@ -118,13 +131,14 @@ enum StencilOp : int {
     OP_F_PAYOFF = 0,   // W = s F(X0), lower faces = payoff
     OP_F_ZERO = 1,     // W = s F(X0), lower faces = 0
     OP_STAGE1 = 2,     // W = s (F(X0) + cG)                  (first stage, X0 = W_n)
-    OP_STAGE2 = 3,     // W = s (F(X0 + a X1) + cG) + q X1    (second stage, X1 = K_1)
+    OP_STAGE2 = 3,     // W = s (F(X0 + a X1) + cG) + q X2    (later stages; AMFR-W2: X1 = X2 = K_1)
     OP_REFINE = 4      // W = 2 W - X0 + s F(X0)              (refinement of eq amfrw)
 };
 
 struct StencilArgs {
     const void* X0;
     const void* X1;
+    const void* X2;       // OP_STAGE2: the vector q multiplies (X1 when null)
     const void* cG;
     void* W;
     void* S;              // non-null: fused axis-0 solve, solved values written here
@@ -157,7 +171,37 @@ struct ResArgs {
     int lds_len;          // padded elements per LDS vector (li of the largest unit)
 };
 
+// out = (acc ? out : 0) + sum_{j < n} c_j in_j over every element of a grid vector.
+constexpr int LIN_MAX = 7;
+struct LinArgs {
+    const void* in[LIN_MAX];
+    double c[LIN_MAX];
+    int n;
+    int acc;
+    void* out;
+};
+
+// (I - theta dt P) x = rhs on every unit, P the lower triangle of the Sketch-1 matrix: one workgroup
+// per unit walks its hyperplanes sum_{i>=1} i (j_i - 1) = const of axis-0 lines; x may overwrite rhs.
+constexpr int LOWER_BLOCK = 256;
+struct LowerArgs {
+    const void* rhs;
+    void* x;
+    int run;              // 0 coarse, 1 fine (Richardson): theta dt from the constant block
+};
+
 // Kernel launchers (amfrw_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_lincomb(const DevPlan& P, int prec, const LinArgs& a, hipStream_t s);
+// flag = index of the first non-finite entry of p[0..n), or -1
+hipError_t launch_first_nonfinite(const double* p, int n, int32_t* flag, hipStream_t s);
+// dst[idx[i]] = src[i], i < n
+hipError_t launch_scatter(const double* src, const int32_t* idx, int n, double* dst, hipStream_t s);
+
+// Surrogate router (amfrw_mlp.hip): network prices and solver-routing flags for n requests.
+amf_status mlp_route(amf_mlp* N, const float* d_x, int64_t n, float tol, float abs_floor, double* d_prices,
+                     int32_t* d_used, hipStream_t s);
+const char* mlp_error();
+hipError_t launch_lower(const DevPlan& P, int prec, const LowerArgs& a, hipStream_t s);
 hipError_t launch_resident(const DevPlan& P, int prec, const ResArgs& a, hipStream_t s);
 hipError_t launch_payoff(const DevPlan& P, int prec, void* Y, hipStream_t s);
 hipError_t launch_fill_zero(const DevPlan& P, int prec, void* Y, hipStream_t s);

@@ -181,7 +181,11 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil(DevPlan P, StencilArgs A
             acc += tmix[i] * s * (xp[i] - xm[i]);
         }
     }
-    const T F = vsq * acc;
+    // nodes on a Dirichlet rate face (eq bound1_0) are boundary data: their row of F is null
+    bool on_face = false;
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) on_face |= dir_face(PR.dirichlet, j[i], M[i]);
+    const T F = on_face ? T(0) : vsq * acc;
     const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
     T* W = (T*)A.W;
     const T* cG = (const T*)A.cG;
@@ -190,7 +194,8 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil(DevPlan P, StencilArgs A
     } else if constexpr (OP == OP_STAGE1) {
         W[g] = sc * (F + cG[g]);
     } else if constexpr (OP == OP_STAGE2) {
-        W[g] = sc * (F + cG[g]) + (T)A.q * X1[g];
+        const T* X2 = A.X2 ? (const T*)A.X2 : X1;
+        W[g] = sc * (F + cG[g]) + (T)A.q * X2[g];
     } else {
         W[g] = T(2) * W[g] - X0[g] + sc * F;
     }
@@ -493,10 +498,15 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
             load_vec<T, R>(W + g, e);     // K^(0)
         }
         T q1[R];
-        if constexpr (OP == OP_STAGE2) load_vec<T, R>(X1 + g, q1);
+        if constexpr (OP == OP_STAGE2) load_vec<T, R>((A.X2 ? (const T*)A.X2 : X1) + g, q1);
+        // Dirichlet rate faces (eq bound1_0): rows of boundary data, F = 0 there
+        const bool dirp = PR.dirichlet != 0;
+        bool rowface = false;
+#pragma unroll
+        for (int k = 1; k < D - 1; ++k) rowface |= dir_face(dirp, j[k], M[k]);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const T F = vsq * acc[r];
+            const T F = (rowface || dir_face(dirp, j[0] + r, M[0])) ? T(0) : vsq * acc[r];
             if constexpr (OP == OP_STAGE1) o[r] = sc * (F + e[r]);
             else if constexpr (OP == OP_STAGE2) o[r] = sc * (F + e[r]) + (T)A.q * q1[r];
             else o[r] = T(2) * e[r] - c[r + 1] + sc * F;
@@ -877,6 +887,7 @@ struct Contig {
     int64_t base;
     const void* tdiff;
     double vsq;
+    int dir;              // Dirichlet upper face (eq bound1_0): the last row is an identity row
 };
 
 template <typename T>
@@ -893,13 +904,15 @@ __device__ __forceinline__ Contig contig_geom(const DevPlan& P, const UnitDev& U
     C.base = U.off + loc0;
     C.tdiff = tab + U.tab[0];
     C.vsq = (double)tab[U.tab[D - 1] + jv];
+    C.dir = P.probs[U.prob].dirichlet;
     return C;
 }
 
 // Short contiguous line: one thread, Thomas with the line in VGPRs.  in/out: the line's M
-// consecutive values (may alias), td: its tdiff factors, cm = V^2 of the line.
+// consecutive values (may alias), td: its tdiff factors, cm = V^2 of the line; dir: the last row
+// sits on a Dirichlet face (identity row: zero coupling).
 template <typename T, int LM>
-__device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm, T nudt)
+__device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm, T nudt, bool dir)
 {
     constexpr int M = 1 << LM;
     T g[M], cp[M];
@@ -907,7 +920,7 @@ __device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm
     for (int r = 0; r < M; ++r) g[r] = in[r];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
-        const T nd = nudt * (td[r] * cm);
+        const T nd = (dir && r == M - 1) ? T(0) : nudt * (td[r] * cm);
         const T b = T(1) + T(2) * nd;
         const T a = (r == 0) ? T(0) : ((r == M - 1) ? -T(2) * nd : -nd);
         const T c = (r == M - 1) ? T(0) : -nd;
@@ -924,7 +937,7 @@ __device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm
 template <typename T, int LM>
 __device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Contig& L, T nudt)
 {
-    reg_solve<T, LM>((const T*)A.in + L.base, (T*)A.out + L.base, (const T*)L.tdiff, (T)L.vsq, nudt);
+    reg_solve<T, LM>((const T*)A.in + L.base, (T*)A.out + L.base, (const T*)L.tdiff, (T)L.vsq, nudt, L.dir != 0);
 }
 
 // Long contiguous line: SP = M/SEG lanes, each owning SEG consecutive rows.  Each lane eliminates
@@ -934,7 +947,7 @@ __device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Conti
 // wavefront shuffles; the lanes then reconstruct their rows.  Diagonally dominant: no pivoting.
 // in/out: the lane's SEG rows (contiguous), td: their tdiff factors, cm = V^2 of the line.
 template <typename T, int SP>
-__device__ __forceinline__ void part_solve(const T* in, T* out, const T* td, T cm, T nudt, int p)
+__device__ __forceinline__ void part_solve(const T* in, T* out, const T* td, T cm, T nudt, int p, bool dir)
 {
     constexpr int S = SEG;
     const bool first = (p == 0), last = (p == SP - 1);
@@ -973,7 +986,7 @@ __device__ __forceinline__ void part_solve(const T* in, T* out, const T* td, T c
     }
     (void)a_first;
     // segment-closing row r0 + S - 1
-    const T ndl = nudt * (td[S - 1] * cm);
+    const T ndl = (dir && last) ? T(0) : nudt * (td[S - 1] * cm);   // Dirichlet face: identity row
     const T bl = T(1) + T(2) * ndl;
     const T al = last ? -T(2) * ndl : -ndl;
     const T cl = last ? T(0) : -ndl;
@@ -1010,7 +1023,7 @@ __device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Cont
 {
     const int r0 = p * SEG;
     part_solve<T, SP>((const T*)A.in + L.base + r0, (T*)A.out + L.base + r0, (const T*)L.tdiff + r0,
-                      (T)L.vsq, nudt, p);
+                      (T)L.vsq, nudt, p, L.dir != 0);
 }
 
 template <typename T, bool LONG>
@@ -1066,7 +1079,8 @@ struct ResGeom {
 // Zero-face Sketch-1 operator on LDS vectors, fused with the stage combination OP.
 template <typename T, int D, int OP>
 __device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const UnitDev& U, const T* tab, const T* cst,
-                                            T sc, T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
+                                            int dirichlet, T sc, T av, T qv, const T* X0, const T* X1, T* Wout,
+                                            const T* cGg)
 {
     for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) {
         int j[D];
@@ -1120,55 +1134,14 @@ __device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const UnitDev& 
                 acc += tmix[i] * sacc * (xp[i] - xm[i]);
             }
         }
-        const T F = vsq * acc;
+        bool face = false;                       // Dirichlet rate faces: null rows
+#pragma unroll
+        for (int i = 0; i < D - 1; ++i) face |= dir_face(dirichlet, j[i], G.M[i]);
+        const T F = face ? T(0) : vsq * acc;
         const int ln = li(n);
         if constexpr (OP == OP_STAGE1) Wout[ln] = sc * (F + cGg[n]);
         else if constexpr (OP == OP_STAGE2) Wout[ln] = sc * (F + cGg[n]) + qv * X1[ln];
         else Wout[ln] = T(2) * Wout[ln] - X0[ln] + sc * F;
-    }
-}
-
-// Axis-0 solves of every line of the unit (LDS in -> LDS out).
-template <typename T, int D>
-__device__ __forceinline__ void res_axis0(const ResGeom<D>& G, const UnitDev& U, const T* tab, T nudt,
-                                          const T* in, T* out)
-{
-    const int lm = U.lv[0];
-    const int lines = G.Pn >> lm;
-    const T* td = tab + U.tab[0];
-    const T* vs = tab + U.tab[D - 1];
-    if (lm <= CONTIG_REG_LM) {
-        for (int line = threadIdx.x; line < lines; line += RES_BLOCK) {
-            const int base = line << lm;
-            const T cm = vs[(base >> G.SV) & (G.MV - 1)];
-            const T* pi = in + li(base);
-            T* po = out + li(base);
-            switch (lm) {
-            case 0: reg_solve<T, 0>(pi, po, td, cm, nudt); break;
-            case 1: reg_solve<T, 1>(pi, po, td, cm, nudt); break;
-            case 2: reg_solve<T, 2>(pi, po, td, cm, nudt); break;
-            case 3: reg_solve<T, 3>(pi, po, td, cm, nudt); break;
-            default: reg_solve<T, 4>(pi, po, td, cm, nudt); break;
-            }
-        }
-    } else {
-        const int sp = (1 << lm) / SEG;
-        const int p = threadIdx.x & (sp - 1);
-        for (int line = threadIdx.x / sp; line < lines; line += RES_BLOCK / sp) {
-            const int base = line << lm;
-            const T cm = vs[(base >> G.SV) & (G.MV - 1)];
-            const int r0 = p * SEG;
-            const T* pi = in + li(base + r0);
-            T* po = out + li(base + r0);
-            switch (lm) {
-            case 5: part_solve<T, 2>(pi, po, td + r0, cm, nudt, p); break;
-            case 6: part_solve<T, 4>(pi, po, td + r0, cm, nudt, p); break;
-            case 7: part_solve<T, 8>(pi, po, td + r0, cm, nudt, p); break;
-            case 8: part_solve<T, 16>(pi, po, td + r0, cm, nudt, p); break;
-            case 9: part_solve<T, 32>(pi, po, td + r0, cm, nudt, p); break;
-            default: part_solve<T, 64>(pi, po, td + r0, cm, nudt, p); break;
-            }
-        }
     }
 }
 
@@ -1250,6 +1223,7 @@ __global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
     const T* cGg = (const T*)A.cG + U.off;
     const T* tab = (const T*)P.tab;
     const T* cst = tab + P.probs[U.prob].cst;
+    const int dirp = P.probs[U.prob].dirichlet;
     const T dt = cst[CST_RUN + 3 * A.run], thdt = cst[CST_RUN + 3 * A.run + 2];
     const T a21 = (T)A.a21, q21 = (T)A.q21, b1 = (T)A.b1, b2 = (T)A.b2;
     const T* fac = (const T*)P.fac + (int64_t)A.run * P.fac_run_stride;
@@ -1257,17 +1231,17 @@ __global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
     __syncthreads();
     for (int st = 0; st < A.nsteps; ++st) {
         // stage 1: K^(0) = dt F(Y); chain; refinement; chain -> K1
-        res_stencil<T, D, OP_STAGE1>(G, U, tab, cst, dt, T(0), T(0), sW, nullptr, sA, cGg);
+        res_stencil<T, D, OP_STAGE1>(G, U, tab, cst, dirp, dt, T(0), T(0), sW, nullptr, sA, cGg);
         __syncthreads();
         res_chain<T, D>(G, U, fac, sA, sB, false, sW, sK, b1, b2);
-        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, thdt, T(0), T(0), sB, nullptr, sA, cGg);
+        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, dirp, thdt, T(0), T(0), sB, nullptr, sA, cGg);
         __syncthreads();
         res_chain<T, D>(G, U, fac, sA, sK, false, sW, sK, b1, b2);
         // stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1; chain; refinement; chain ending in the update
-        res_stencil<T, D, OP_STAGE2>(G, U, tab, cst, dt, a21, q21, sW, sK, sA, cGg);
+        res_stencil<T, D, OP_STAGE2>(G, U, tab, cst, dirp, dt, a21, q21, sW, sK, sA, cGg);
         __syncthreads();
         res_chain<T, D>(G, U, fac, sA, sB, false, sW, sK, b1, b2);
-        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, thdt, T(0), T(0), sB, nullptr, sA, cGg);
+        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, dirp, thdt, T(0), T(0), sB, nullptr, sA, cGg);
         __syncthreads();
         res_chain<T, D>(G, U, fac, sA, sB, true, sW, sK, b1, b2);
     }
@@ -1333,6 +1307,190 @@ __global__ void k_combine(DevPlan P, const double* coef, const double* vals, con
     double price = PR.discount * s;
     if (coarse) price = (8.0 * price - PR.discount * sc) / 7.0;
     prices[p] = price;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Stage combinations of schemes with more than two stages: out = (acc ? out : 0) + sum_j c_j in_j
+// over every element (padding included, which stays 0).  Four elements per thread.
+template <typename T>
+__global__ __launch_bounds__(NODE_BLOCK) void k_lincomb(int64_t total, LinArgs A)
+{
+    const int64_t g0 = ((int64_t)blockIdx.x * NODE_BLOCK + threadIdx.x) * 4;
+    if (g0 >= total) return;                  // total is a multiple of UNIT_ALIGN (>= 4)
+    T v[4];
+    T* out = (T*)A.out;
+    if (A.acc) load_vec<T, 4>(out + g0, v);
+    else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) v[r] = T(0);
+    }
+#pragma unroll
+    for (int j = 0; j < LIN_MAX; ++j) {
+        if (j < A.n) {
+            T w[4];
+            load_vec<T, 4>((const T*)A.in[j] + g0, w);
+            const T c = (T)A.c[j];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] += c * w[r];
+        }
+    }
+    store_vec<T, 4>(out + g0, v);
+}
+
+// ------------------------------------------------------------------------------------------------
+// (I - theta dt P) x = rhs, P the lower triangle (diagonal included) of the Sketch-1 matrix in the
+// theta_0 order (Section 4.2, eq (GS)), on every unit.  Row J reads x at its lower neighbours: J - E_0
+// on its own axis-0 line, and J - E_k, J - E_i - E_k, J + E_i - E_k (i < k, k >= 1) on axis-0 lines
+// whose index r = (j_1, .., j_{d-1}) has a smaller h(r) = sum_{i>=1} i (j_i - 1).  The lines of one
+// hyperplane h = const are therefore independent: one workgroup per unit walks the hyperplanes in
+// order with a barrier between them (the host lists each unit's lines by hyperplane).  Along a line
+// the row recurrence x_j = alpha_j + beta_j x_{j-1} is split into `lanes` segments of ROWS rows,
+// segments on consecutive lanes of one wave, joined by a shuffle scan of their affine maps.
+// Neighbours on a lower face are 0 (stage increments); Dirichlet rate faces (eq bound1_0) are 0.
+template <typename T, int D, int ROWS>
+__device__ __forceinline__ void lower_segment(const DevPlan& P, const UnitDev& U, const ProbDev& PR,
+                                              const T* tab, const T* cst, T thdt, const T* rhs, T* x,
+                                              int64_t line, bool live, int pos, int lanes)
+{
+    T al[ROWS], be[ROWS];
+    int M[D], Sh[D], j[D];
+    {
+        int sh = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            M[i] = 1 << U.lv[i];
+            Sh[i] = sh;
+            sh += U.lv[i];
+        }
+    }
+    const int64_t lbase = live ? (line << U.lv[0]) : 0;     // loc of the line's first row
+#pragma unroll
+    for (int i = 1; i < D; ++i) j[i] = (int)((lbase >> Sh[i]) & (M[i] - 1)) + 1;
+    const T* tV = tab + U.tab[D - 1];
+    const int MV = M[D - 1];
+    const T vsq = tV[j[D - 1] - 1];
+    // per-line factors of the axes 1..d-1 (the line's j_1..j_{d-1} are fixed)
+    T tdiff[D], tmix[D], tphi[D];
+    tdiff[D - 1] = tV[MV];
+    tmix[D - 1] = tV[MV + 1];
+    tphi[D - 1] = T(0);
+#pragma unroll
+    for (int i = 1; i < D - 1; ++i) {
+        const T* ti = tab + U.tab[i];
+        tdiff[i] = ti[j[i] - 1];
+        tmix[i] = ti[M[i] + j[i] - 1];
+        tphi[i] = ti[2 * M[i] + j[i] - 1];
+    }
+    bool rowface = false;
+#pragma unroll
+    for (int i = 1; i < D - 1; ++i) rowface |= dir_face(PR.dirichlet, j[i], M[i]);
+    const T* t0 = tab + U.tab[0];
+    T y = T(0), mu = T(1);
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int j0 = pos * ROWS + k + 1;
+            const int64_t J = lbase + (j0 - 1);
+            tdiff[0] = t0[j0 - 1];
+            tmix[0] = t0[M[0] + j0 - 1];
+            T sd = T(0);
+#pragma unroll
+            for (int i = 0; i < D; ++i) sd += tdiff[i];
+            const T diag = T(1) + thdt * vsq * (T(2) * sd);
+            T known = T(0);
+            // J - E_k, k >= 1: second difference (doubled by the Neumann ghost at j_k = M_k) and the
+            // advection of paper axes 2..N-1 (none on the upper face)
+#pragma unroll
+            for (int k1 = 1; k1 < D; ++k1) {
+                if (j[k1] > 1) {
+                    T c = tdiff[k1] * (j[k1] == M[k1] ? T(2) : T(1));
+                    if (k1 < D - 1 && j[k1] != M[k1]) {
+                        T sa = T(0);
+#pragma unroll
+                        for (int jj = 1; jj <= k1; ++jj) sa += cst[CST_RHO + k1 * MAXD + jj] * tphi[jj];
+                        c -= tmix[k1] * sa;
+                    }
+                    known += c * x[J - ((int64_t)1 << Sh[k1])];
+                }
+            }
+            // mixed pairs (i, k), i < k: J - E_i - E_k (+) and J + E_i - E_k (-), none on an upper face
+#pragma unroll
+            for (int i = 0; i < D - 1; ++i) {
+#pragma unroll
+                for (int k1 = i + 1; k1 < D; ++k1) {
+                    const int ji = i == 0 ? j0 : j[i];
+                    if (ji == M[i] || j[k1] == M[k1] || j[k1] == 1) continue;
+                    const T cik = ((k1 < D - 1) ? cst[CST_RHO + i * MAXD + k1] : cst[CST_SPHI + i]) *
+                                  tmix[i] * tmix[k1];
+                    const int64_t Ei = (int64_t)1 << Sh[i], Ek = (int64_t)1 << Sh[k1];
+                    T v = -x[J + Ei - Ek];
+                    if (ji > 1) v += x[J - Ei - Ek];
+                    known += cik * v;
+                }
+            }
+            const bool face = rowface || dir_face(PR.dirichlet, j0, M[0]);
+            const T a = face ? T(0) : (rhs[J] + thdt * vsq * known) / diag;
+            const T b = (face || j0 == 1) ? T(0)
+                                          : thdt * vsq * tdiff[0] * (j0 == M[0] ? T(2) : T(1)) / diag;
+            al[k] = a;
+            be[k] = b;
+            y = a + b * y;
+            mu = b * mu;
+        }
+    }
+    // carry entering the segment: the value of x at the row before it (0 before the line)
+    const T xin = wave_carry<T>(mu, y, pos, lanes, false);
+    if (live) {
+        T xv = xin;
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            xv = al[k] + be[k] * xv;
+            x[lbase + pos * ROWS + k] = xv;
+        }
+    }
+}
+
+template <typename T, int D, int ROWS>
+__device__ __forceinline__ void lower_unit(const DevPlan& P, const UnitDev& U, int u, const LowerArgs& A)
+{
+    const ProbDev& PR = P.probs[U.prob];
+    const T* tab = (const T*)P.tab;
+    const T* cst = tab + PR.cst;
+    const T thdt = cst[CST_RUN + 3 * A.run + 2];
+    const T* rhs = (const T*)A.rhs + U.off;
+    T* x = (T*)A.x + U.off;
+    const int M0 = 1 << U.lv[0];
+    const int lanes = M0 / ROWS;                        // segments per line (<= 64)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int per_wave = 64 / lanes;
+    const int slots = per_wave * (LOWER_BLOCK / 64);
+    const int slot = wave * per_wave + lane / lanes;
+    const int pos = lane % lanes;
+    for (int p = P.gs_unit_plane0[u]; p < P.gs_unit_plane0[u + 1]; ++p) {
+        const int64_t l0 = P.gs_plane_line0[p], l1 = P.gs_plane_line0[p + 1];
+        for (int64_t b = l0; b < l1; b += slots) {      // block-uniform trip count
+            const int64_t k = b + slot;
+            const bool live = k < l1;
+            const int64_t line = live ? P.gs_lines[k] : 0;
+            lower_segment<T, D, ROWS>(P, U, PR, tab, cst, thdt, rhs, x, line, live, pos, lanes);
+        }
+        __syncthreads();                                // the plane's rows before the next plane's
+    }
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(LOWER_BLOCK) void k_lower(DevPlan P, LowerArgs A)
+{
+    const int u = blockIdx.x;
+    const UnitDev U = P.units[u];
+    // rows per lane: lines up to 64 rows take one lane per row, longer ones 64 lanes (<= 16 rows each)
+    switch (U.lv[0] <= 6 ? 0 : U.lv[0] - 6) {          // block-uniform
+    case 0: lower_unit<T, D, 1>(P, U, u, A); break;
+    case 1: lower_unit<T, D, 2>(P, U, u, A); break;
+    case 2: lower_unit<T, D, 4>(P, U, u, A); break;
+    case 3: lower_unit<T, D, 8>(P, U, u, A); break;
+    default: lower_unit<T, D, 16>(P, U, u, A); break;  // axis-1 levels above 10 are rejected
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1470,6 +1628,78 @@ hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part,
         else sweep_part<float, true>(P, axis, epi, a, b0, nb, s);
     }
     return hipGetLastError();
+}
+
+// Index of the first non-finite price (-1 if none): one block, min-reduction in LDS.
+__global__ __launch_bounds__(256) void k_first_nonfinite(const double* p, int n, int32_t* flag)
+{
+    __shared__ int best[256];
+    int m = INT32_MAX;
+    for (int i = threadIdx.x; i < n; i += 256)
+        if (!isfinite(p[i]) && i < m) m = i;
+    best[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) best[threadIdx.x] = min(best[threadIdx.x], best[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) flag[0] = best[0] == INT32_MAX ? -1 : best[0];
+}
+
+__global__ void k_scatter(const double* src, const int32_t* idx, int n, double* dst)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[idx[i]] = src[i];
+}
+
+hipError_t launch_first_nonfinite(const double* p, int n, int32_t* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_first_nonfinite, dim3(1), dim3(256), 0, s, p, n, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double* src, const int32_t* idx, int n, double* dst, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, src, idx, n, dst);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t lincomb_t(const DevPlan& P, const LinArgs& a, hipStream_t s)
+{
+    const int64_t nb = (P.total / 4 + NODE_BLOCK - 1) / NODE_BLOCK;
+    hipLaunchKernelGGL((k_lincomb<T>), dim3((unsigned)nb), dim3(NODE_BLOCK), 0, s, P.total, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lincomb(const DevPlan& P, int prec, const LinArgs& a, hipStream_t s)
+{
+    if (P.total == 0) return hipSuccess;
+    if (a.n < 0 || a.n > LIN_MAX || (P.total & 3)) return hipErrorInvalidValue;
+    return prec == 0 ? lincomb_t<double>(P, a, s) : lincomb_t<float>(P, a, s);
+}
+
+template <typename T>
+static hipError_t lower_t(const DevPlan& P, const LowerArgs& a, hipStream_t s)
+{
+    dim3 g((unsigned)P.n_units), b(LOWER_BLOCK);
+    switch (P.d) {
+    case 2: hipLaunchKernelGGL((k_lower<T, 2>), g, b, 0, s, P, a); break;
+    case 3: hipLaunchKernelGGL((k_lower<T, 3>), g, b, 0, s, P, a); break;
+    case 4: hipLaunchKernelGGL((k_lower<T, 4>), g, b, 0, s, P, a); break;
+    case 5: hipLaunchKernelGGL((k_lower<T, 5>), g, b, 0, s, P, a); break;
+    case 6: hipLaunchKernelGGL((k_lower<T, 6>), g, b, 0, s, P, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_lower(const DevPlan& P, int prec, const LowerArgs& a, hipStream_t s)
+{
+    if (P.n_units == 0) return hipSuccess;
+    if (!P.gs_unit_plane0 || !P.gs_plane_line0 || !P.gs_lines) return hipErrorInvalidValue;
+    return prec == 0 ? lower_t<double>(P, a, s) : lower_t<float>(P, a, s);
 }
 
 template <typename T>

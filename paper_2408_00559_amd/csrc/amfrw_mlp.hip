@@ -11,6 +11,7 @@
 // so the forward pass also stores activations transposed and the backward pass stores dZ^T.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -147,6 +148,27 @@ __global__ void k_output(const float* Y, int batch, int ldy, const float* omean,
     out[2 * b + 1] = lg ? e : e / fmaxf(fabsf(price), 1e-30f);
 }
 
+// Router of the price_or_fallback call: request b is served by the network when its features lie in
+// the training box [lo, hi], its price p is finite and its calibrated error estimate e = calib est
+// satisfies e <= tol or e |p| <= abs_floor; used[b] = 1 routes it to the solver.
+__global__ void k_route(const float* out, const float* x, int batch, int nin, const float* box, float calib,
+                        float tol, float abs_floor, double* prices, int32_t* used)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    bool inside = true;
+    for (int c = 0; c < nin; ++c) {
+        const float v = x[(size_t)b * nin + c];
+        inside = inside && v >= box[c] && v <= box[32 + c];
+    }
+    const float p = out[2 * b + 0];
+    const float e = calib * out[2 * b + 1];
+    const bool finite = isfinite(p) && isfinite(e);
+    const bool ok = inside && finite && (e <= tol || e * fabsf(p) <= abs_floor);
+    prices[b] = (double)p;
+    used[b] = ok ? 0 : 1;
+}
+
 // Loss and output gradient.  t = (target - m0)/s0, r = y0 - t;
 //   L = mean_b [ r^2 + w (y1 - log(|r| + eps))^2 ]   (the second term trains the error head on the
 //   detached residual).  dY is written in BF16 row-major and transposed; padding rows/cols are 0.
@@ -271,6 +293,9 @@ struct amf_mlp {
     size_t o_p = 0, o_g = 0, o_m = 0, o_v = 0, o_mask = 0, o_bfi = 0, o_bfti = 0, o_wbf = 0;
     size_t o_norm = 0, o_x = 0, o_xt = 0, o_z[MAX_LAYERS]{}, o_a[MAX_LAYERS]{}, o_at[MAX_LAYERS]{};
     size_t o_dy = 0, o_dyt = 0, o_dz = 0, o_dzt = 0, o_dzb = 0, o_dztb = 0, o_rl = 0, o_loss = 0;
+    size_t o_route = 0, o_box = 0;   // router: network outputs [max_batch, 2]; box lo[32], hi[32]
+    float calib = 1.0f;
+    bool have_router = false;
     size_t ws_bytes = 0;
     char* ws = nullptr;
     int64_t t = 0;                   // Adam step
@@ -490,6 +515,8 @@ amf_status amf_mlp_create(int32_t n_in, int32_t width, int32_t depth, int32_t n_
     N->o_dztb = take((size_t)bp * width * 2);
     N->o_rl = take((size_t)bp * 4);
     N->o_loss = take(16);
+    N->o_route = take((size_t)max_batch * 2 * 4);
+    N->o_box = take(64 * 4);
     N->ws_bytes = o;
     *out = N;
     return AMF_OK;
@@ -600,6 +627,23 @@ amf_status amf_mlp_forward(amf_mlp* N, const float* d_x, int32_t batch, float* d
     return hipchk(hipGetLastError(), "output");
 }
 
+amf_status amf_mlp_set_router(amf_mlp* N, const float* box_lo, const float* box_hi, float calib)
+{
+    if (!N || !N->ws || !box_lo || !box_hi) return mfail(AMF_E_INVALID, "null argument");
+    if (!(calib > 0.0f) || !std::isfinite(calib)) return mfail(AMF_E_INVALID, "calib must be > 0");
+    float box[64];
+    for (int c = 0; c < 32; ++c) {
+        box[c] = c < N->n_in ? box_lo[c] : 0.0f;
+        box[32 + c] = c < N->n_in ? box_hi[c] : 0.0f;
+        if (c < N->n_in && !(box_lo[c] <= box_hi[c])) return mfail(AMF_E_INVALID, "box_lo must be <= box_hi");
+    }
+    hipError_t e = hipMemcpy(N->ws + N->o_box, box, sizeof(box), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hipchk(e, "upload");
+    N->calib = calib;
+    N->have_router = true;
+    return AMF_OK;
+}
+
 amf_status amf_mlp_backward(amf_mlp* N, const float* d_dy, int32_t batch, void* stream)
 {
     if (!N || !N->ws || !d_dy) return mfail(AMF_E_INVALID, "null argument");
@@ -648,3 +692,29 @@ amf_status amf_mlp_train_step(amf_mlp* N, const float* d_x, const float* d_targe
 void amf_mlp_destroy(amf_mlp* N) { delete N; }
 
 }  // extern "C"
+
+namespace amf {
+
+// Network prices and routing decisions for n requests (chunks of max_batch): d_prices[i] = the
+// network's price, d_used[i] = 1 when request i must go to the solver.
+amf_status mlp_route(amf_mlp* N, const float* d_x, int64_t n, float tol, float abs_floor, double* d_prices,
+                     int32_t* d_used, hipStream_t s)
+{
+    if (!N || !N->ws || !d_x || !d_prices || !d_used) return mfail(AMF_E_INVALID, "null argument");
+    if (!N->have_router) return mfail(AMF_E_STATE, "amf_mlp_set_router has not been called");
+    if (!(tol >= 0.0f) || !(abs_floor >= 0.0f)) return mfail(AMF_E_INVALID, "tol and abs_floor must be >= 0");
+    float* out = (float*)(N->ws + N->o_route);
+    for (int64_t c0 = 0; c0 < n; c0 += N->max_batch) {
+        const int b = (int)std::min<int64_t>(N->max_batch, n - c0);
+        amf_status st = amf_mlp_forward(N, d_x + c0 * N->n_in, b, out, s);
+        if (st) return st;
+        hipLaunchKernelGGL(k_route, dim3((b + 255) / 256), dim3(256), 0, s, out, d_x + c0 * N->n_in, b, N->n_in,
+                           (const float*)(N->ws + N->o_box), N->calib, tol, abs_floor, d_prices + c0, d_used + c0);
+        if ((st = hipchk(hipGetLastError(), "route"))) return st;
+    }
+    return AMF_OK;
+}
+
+const char* mlp_error() { return g_mlp_err.c_str(); }
+
+}  // namespace amf

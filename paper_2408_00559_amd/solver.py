@@ -8,9 +8,10 @@ from typing import List, Sequence
 import torch
 
 from . import _lib as L
-from .inputs import CAPLET, GridSpec, Problem
+from .inputs import CAPLET, DIRICHLET, NEUMANN, GridSpec, Problem
 
 PAYOFF = {CAPLET: L.PAYOFF_CAPLET, "swaption": L.PAYOFF_SWAPTION}
+BOUNDARY = {NEUMANN: L.BC_NEUMANN, DIRICHLET: L.BC_DIRICHLET}
 
 
 def problem_struct(p: Problem) -> L.AmfProblem:
@@ -18,6 +19,7 @@ def problem_struct(p: Problem) -> L.AmfProblem:
     s.struct_size = C.sizeof(L.AmfProblem)
     s.d = p.d
     s.payoff = PAYOFF[p.payoff]
+    s.boundary = BOUNDARY[p.boundary]
     s.beta = p.beta
     s.sigma = p.sigma
     for i in range(p.d - 1):
@@ -52,6 +54,29 @@ def scheme_amfrw2(nu: float | None = None) -> L.AmfScheme:
     L.check(L.lib().amf_scheme_amfrw2(C.byref(s)))
     if nu is not None:
         s.nu = nu
+    return s
+
+
+def scheme_theta_gs(theta: float, stages: int) -> L.AmfScheme:
+    """theta-method with `stages` Gauss-Seidel sweeps as a W-method (W = P)."""
+    s = L.AmfScheme()
+    L.check(L.lib().amf_scheme_theta_gs(float(theta), int(stages), C.byref(s)))
+    return s
+
+
+def scheme_generic(a, q, b, theta: float, nu: float, w_matrix: int = L.W_AMF) -> L.AmfScheme:
+    """A W-method table: a[r][j], q[r][j] for j < r, b[r]; W the AMF W or the lower triangle P."""
+    s = L.AmfScheme()
+    s.struct_size = C.sizeof(L.AmfScheme)
+    s.stages = len(b)
+    for r in range(len(b)):
+        s.b[r] = b[r]
+        for j in range(r):
+            s.a[r * L.MAX_STAGES + j] = a[r][j]
+            s.q[r * L.MAX_STAGES + j] = q[r][j]
+    s.theta = theta
+    s.nu = nu
+    s.w_matrix = w_matrix
     return s
 
 
@@ -136,6 +161,13 @@ class Plan:
         if out is None:
             out = torch.empty(len(self.problems), dtype=torch.float64, device=self.device)
         L.check(L.lib().amf_combine(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def combine_checked(self, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """combine(), then wait and raise AmfError(AMF_E_NUMERIC) if a price is not finite."""
+        if out is None:
+            out = torch.empty(len(self.problems), dtype=torch.float64, device=self.device)
+        L.check(L.lib().amf_combine_checked(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
         return out
 
     def unit_values(self, stream=None) -> torch.Tensor:

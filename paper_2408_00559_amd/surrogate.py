@@ -48,6 +48,10 @@ def _mlp_lib():
         lib.amf_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.c_float, vp, vp]
         lib.amf_mlp_destroy.restype = None
         lib.amf_mlp_destroy.argtypes = [vp]
+        lib.amf_mlp_set_router.restype = st
+        lib.amf_mlp_set_router.argtypes = [vp, fp, fp, C.c_float]
+        lib.amf_price_or_fallback.restype = st
+        lib.amf_price_or_fallback.argtypes = [vp, vp, vp, C.c_float, C.c_float, vp, vp, vp]
         lib._mlp_ready = True
     return lib
 
@@ -98,6 +102,25 @@ class Mlp:
                      float(out_std), bool(out_log))
         _check(_mlp_lib().amf_mlp_set_normalization(self._h, f(in_mean), f(in_std), f([out_mean]), f([out_std]),
                                                     1 if out_log else 0, _stream()))
+
+    def set_router(self, box_lo, box_hi, calib: float):
+        """Training box and calibration factor used by price_or_fallback."""
+        f = lambda a: (C.c_float * self.n_in)(*[float(v) for v in a])
+        _check(_mlp_lib().amf_mlp_set_router(self._h, f(box_lo), f(box_hi), float(calib)))
+
+    def price_or_fallback(self, plan: Plan, x: torch.Tensor, tol: float, abs_floor: float = 0.0):
+        """Prices of the plan's problems (FP64) and the 0/1 solver-routing flags, decided and computed
+        in the library: the network where it is trusted, the plan's solver elsewhere."""
+        x = x.to(device=self.device, dtype=torch.float32).contiguous()
+        n = len(plan.problems)
+        assert x.shape == (n, self.n_in)
+        prices = torch.empty(n, dtype=torch.float64, device=self.device)
+        used = torch.empty(n, dtype=torch.int32, device=self.device)
+        st = _mlp_lib().amf_price_or_fallback(self._h, plan._h, C.c_void_p(x.data_ptr()), float(tol),
+                                              float(abs_floor), C.c_void_p(prices.data_ptr()),
+                                              C.c_void_p(used.data_ptr()), _stream())
+        L.check(st)
+        return prices, used
 
     def params(self) -> torch.Tensor:
         out = torch.empty(int(self.info.n_params), dtype=torch.float32, device=self.device)
@@ -180,6 +203,7 @@ class Surrogate:
         p, err = self.predict(x)
         ratio = (np.abs(p - y) / np.abs(y)) / np.maximum(err, 1e-30)
         self.calib = float(np.quantile(ratio, q))
+        self.mlp.set_router(self.box_lo, self.box_hi, self.calib)
         return self.calib
 
     @staticmethod
@@ -211,26 +235,28 @@ class Surrogate:
                 k += 1
             if log is not None and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
                 log("epoch %d loss %.3e" % (ep, loss.item() / batch))
-        return Surrogate(mlp, x.min(axis=0), x.max(axis=0), grid, steps)
+        sur = Surrogate(mlp, x.min(axis=0), x.max(axis=0), grid, steps)
+        mlp.set_router(sur.box_lo, sur.box_hi, sur.calib)
+        return sur
 
     def predict(self, x: np.ndarray):
         """(price, estimated relative error before calibration) from the network."""
         out = self.mlp.forward(torch.tensor(x, dtype=torch.float32)).cpu().numpy()
         return out[:, 0].astype(np.float64), out[:, 1].astype(np.float64)
 
-    def price(self, problems: Sequence[I.Problem], tol: float = 1e-4, precision: str = "fp32"):
-        """Prices with fallback: the network's price where its estimated relative error is at most
-        `tol` and the request lies inside the training box, else the solver's.  Returns (prices,
-        used_solver mask, seconds spent in the network, seconds spent in the solver)."""
-        x = features(problems)
+    def price(self, problems: Sequence[I.Problem], tol: float = 1e-4, precision: str = "fp32",
+              abs_floor: float = 0.0, plan: Plan | None = None):
+        """Prices with fallback, decided and computed in the library (amf_price_or_fallback): the
+        network's price where the request lies inside the training box and its calibrated error
+        estimate is within `tol` (relative) or `abs_floor` (absolute), else the solver's.  `plan`
+        (built here when not given) holds the requests' problems and is the solver.  Returns
+        (prices, used_solver mask, seconds)."""
+        from . import autotune
+        if plan is None:
+            plan = Plan(problems, self.grid, self.steps, precision=precision, device=str(self.mlp.device))
+            autotune.tune(plan, steps=1, reps=1)
+        x = torch.tensor(features(problems), dtype=torch.float32, device=self.mlp.device)
         t0 = time.perf_counter()
-        p, err = self.predict(x)
-        t1 = time.perf_counter()
-        inside = np.all((x >= self.box_lo) & (x <= self.box_hi), axis=1)
-        use_solver = (~inside) | (err * self.calib > tol) | ~np.isfinite(p)
-        idx = np.nonzero(use_solver)[0]
-        t2 = time.perf_counter()
-        if len(idx):
-            p[idx] = solver_prices([problems[i] for i in idx], self.grid, self.steps, precision)
-        t3 = time.perf_counter()
-        return p, use_solver, t1 - t0, t3 - t2
+        prices, used = self.mlp.price_or_fallback(plan, x, tol, abs_floor)
+        dt = time.perf_counter() - t0
+        return prices.cpu().numpy(), used.cpu().numpy().astype(bool), dt

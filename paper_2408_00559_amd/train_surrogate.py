@@ -121,7 +121,7 @@ def train(a, log):
     for tol in (1e-4, 1e-3, 1e-2, 3e-2):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        pp, used, tn, tf = sur.price(hp[:ns], tol=tol)
+        pp, used, _ = sur.price(hp[:ns], tol=tol)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         r = np.abs(pp - yh[:ns]) / np.abs(yh[:ns])

@@ -4,6 +4,9 @@ Calls only the CPU oracle (oracle/) and the input definitions (paper_2408_00559_
 Usage:  python tests/golden/make_golden.py ct4 [threads]      (d=4, n=7, psi=3, 100 steps, FP64)
         python tests/golden/make_golden.py batch4 [threads]   (first 16 of the 512 seeded instances)
         python tests/golden/make_golden.py ct6 [threads]      (d=6, n=8, psi=1: sampled grids, 400 steps)
+        python tests/golden/make_golden.py ct6all [threads]   (d=6, n=8, psi=1: every grid, both
+                                                               Richardson runs, 8 + 16 steps at the
+                                                               workload's dt)
 """
 import json
 import os
@@ -83,6 +86,35 @@ def run_ct6(threads):
     _dump(out, "ct6_n8_psi1_sampled_fp64.json")
 
 
+CT6_SHORT_STEPS = 8
+
+
+def ct6_short_workload():
+    """The d = 6 workload over a shortened horizon: the same problem, grids and step sizes
+    (coarse dt = T / 200, fine dt / 2), but T' = 8 dt, so the coarse run takes 8 steps and the fine
+    run 16.  (The full 200 + 400 steps over all 2,975 grids take about 11 CPU-hours in the oracle.)"""
+    w = I.workload_ct6()
+    p = w["problems"][0]
+    p.T = p.T * CT6_SHORT_STEPS / w["steps"]
+    return dict(w, problems=[p], steps=CT6_SHORT_STEPS, name=w["name"] + "_short")
+
+
+def run_ct6all(threads):
+    w = ct6_short_workload()
+    p = w["problems"][0]
+    t = time.time()
+    price, (uc, uf) = oracle.price(p, w["grid"], w["steps"], nthreads=threads, richardson=True,
+                                   return_units=True)
+    lv, cf = oracle.ct_grids(p.d, w["grid"].n, w["grid"].psi)
+    out = dict(workload=w["name"], maturity=p.T, steps=w["steps"], price=price,
+               unit_levels=lv.tolist(), unit_coef=cf.tolist(),
+               unit_values_coarse=list(map(float, uc)), unit_values_fine=list(map(float, uf)),
+               oracle_seconds=time.time() - t, threads=threads,
+               note="FP64 CPU oracle, every component grid, Richardson pair, written by "
+                    "tests/golden/make_golden.py")
+    _dump(out, "ct6_n8_psi1_short_all_fp64.json")
+
+
 def reformat(name):
     """Rewrite an existing file in the layout above (values unchanged)."""
     _dump(json.load(open(os.path.join(HERE, name))), name)
@@ -94,4 +126,4 @@ if __name__ == "__main__":
         reformat(sys.argv[2])
         sys.exit(0)
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    {"ct4": run_ct4, "batch4": run_batch4, "ct6": run_ct6}[which](threads)
+    {"ct4": run_ct4, "batch4": run_batch4, "ct6": run_ct6, "ct6all": run_ct6all}[which](threads)

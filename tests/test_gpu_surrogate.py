@@ -1,5 +1,7 @@
 """GPU parity of the surrogate network (BF16 MFMA kernels) against the FP64 CPU reference with the
 same BF16 rounding points, training progress, and the surrogate-with-fallback against the solver."""
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -97,12 +99,25 @@ def test_surrogate_gain_with_fallback():
     sur = S.Surrogate.train(S.features(train), ytr, grid, steps, epochs=300, batch=512, device=DEV)
     sur.calibrate(S.features(cal), S.solver_prices(cal, grid, steps))
     torch.cuda.synchronize()
-    import time
     t0 = time.perf_counter()
     yref = S.solver_prices(held, grid, steps)
     t_solver = time.perf_counter() - t0
     tol = 3e-2
-    p, used, t_net, t_fb = sur.price(held, tol=tol)
+    xh = S.features(held)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pn, est = sur.predict(xh)
+    t_net = time.perf_counter() - t0
+    p, used, _ = sur.price(held, tol=tol)
+    # the library's routing equals the rule written out here, decision for decision (in FP32, the
+    # precision the library decides in): inside the training box, finite, calibrated estimate
+    # within the relative tolerance
+    f32 = np.float32
+    inside = np.all((xh.astype(f32) >= sur.box_lo.astype(f32)) & (xh.astype(f32) <= sur.box_hi.astype(f32)), axis=1)
+    e32 = f32(sur.calib) * est.astype(f32)
+    expect = ~(inside & np.isfinite(pn) & np.isfinite(e32) & (e32 <= f32(tol)))
+    assert np.array_equal(used, expect)
+    np.testing.assert_allclose(p[~used], pn[~used].astype(np.float32).astype(np.float64), rtol=0, atol=0)
     rel = np.abs(p - yref) / np.abs(yref)
     served = ~used
     assert served.sum() > 0
@@ -113,9 +128,12 @@ def test_surrogate_gain_with_fallback():
     # the calibrated error estimate is an honest filter: served prices meet the tolerance up to the
     # calibration quantile
     assert np.quantile(rel[served], 0.9) < tol, np.quantile(rel[served], 0.9)
+    # an absolute floor serves more requests, never fewer
+    _, used_f, _ = sur.price(held, tol=tol, abs_floor=1e-4)
+    assert np.all(used_f <= used) and used_f.sum() < used.sum() or used.sum() == 0
     # requests outside the training box (maturity beyond its range) always go to the solver
     outside = I.draw_instances(8, seed=53, d=4, T_range=(2.0, 2.5), lam_range=(0.05, 0.3))
-    po, used_o, _, _ = sur.price(outside, tol=1.0)
+    po, used_o, _ = sur.price(outside, tol=1.0)
     assert used_o.all()
     yo = S.solver_prices(outside, grid, steps)
     assert np.max(np.abs(po - yo) / np.abs(yo)) < 1e-6

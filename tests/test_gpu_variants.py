@@ -1,0 +1,267 @@
+"""GPU parity of the variants against the FP64 CPU oracle, through the C ABI: the Dirichlet upper
+rate faces of eq. (bound1_0), generic stage counts of eq. (row-s) with the AMF W, the W = P method
+of Section 4.2 (theta-method + Gauss-Seidel, wavefront lower-triangular solves), and the checked
+combination that reports non-finite prices.  Bars as in test_gpu_parity.py: FP64 1e-10 relative per
+price and 1e-12 of the max-norm per step, FP32 1e-5 per price."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_00559_amd import _lib as L
+from paper_2408_00559_amd import inputs as I
+from paper_2408_00559_amd import solver as S
+from paper_2408_00559_amd.solver import Plan
+
+from _util import parallel, rel_maxerr, unit_slices
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _mixed_bc(probs):
+    """Alternate the boundary kinds inside one plan."""
+    for i, p in enumerate(probs):
+        p.boundary = I.DIRICHLET if i % 2 == 0 else I.NEUMANN
+    return probs
+
+
+def _cases():
+    return {
+        "fg2d_dir": (_mixed_bc(I.workload_fg2d()["problems"]), I.full_grid([6, 5])),
+        "d2_long_axis0_dir": (_mixed_bc(I.workload_fg2d()["problems"]), I.full_grid([9, 3])),
+        "d3_ragged_dir": (_mixed_bc(I.draw_instances(1, seed=33, d=3)), I.full_grid([6, 0, 5])),
+        "d3_ct_mixed": (_mixed_bc(I.draw_instances(2, seed=31, d=3)), I.combination(4, 1)),
+        "d4_ct_mixed": (_mixed_bc(I.draw_instances(3, seed=41, d=4)), I.combination(4, 1)),
+        "d2_standard_ct_dir": (_mixed_bc([I.paper_caplet(sigma=0.3, phi=0.4)]), I.combination(6, 0)),
+        "d6_ct_dir": (_mixed_bc(I.draw_instances(1, seed=61, d=6)), I.combination(5, 1)),
+    }
+
+
+CASES = _cases()
+
+
+def _outer_mask(p, levels):
+    """Inner-node layout mask of the Dirichlet rate faces (boundary data under eq. bound1_0)."""
+    M = [1 << l for l in levels]
+    shp = tuple(reversed(M))
+    idx = np.indices(shp).reshape(len(M), -1)[::-1] + 1            # axis 0 fastest, 1-based
+    if p.boundary != I.DIRICHLET:
+        return np.zeros(idx.shape[1], dtype=bool)
+    return np.any(idx[:-1] == np.array(M[:-1])[:, None], axis=0)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dirichlet_operator_on_increments(name):
+    """Sketch 1 on a random increment (0 on every Outer node, Dirichlet rate faces included)."""
+    import torch
+    probs, grid = CASES[name]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    x = np.random.default_rng(3).uniform(-1, 1, plan.vector_len)
+    for u, sl in unit_slices(plan):
+        x[sl] = np.where(_outer_mask(probs[u["problem"]], u["levels"]), 0.0, x[sl])
+    out = plan.apply_operator(torch.tensor(x, device=DEV), True, 0.7).cpu().numpy()
+
+    def ref(item):
+        u, sl = item
+        p, lv = probs[u["problem"]], u["levels"]
+        return 0.7 * oracle.inner_view(oracle.eval_F(p, lv, oracle.full_from_inner(x[sl], lv)), lv)
+
+    items = unit_slices(plan)
+    for (u, sl), r in zip(items, parallel(ref, items)):
+        assert rel_maxerr(out[sl], r) < 1e-12, (u, rel_maxerr(out[sl], r))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dirichlet_operator_on_payoff(name):
+    """F(g) with the payoff on every stored node (faces included), as the solver forms it."""
+    probs, grid = CASES[name]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    plan.init()
+    g = plan.state()
+    out = plan.apply_operator(g, False, 1.0).cpu().numpy()
+
+    def ref(item):
+        u, sl = item
+        p, lv = probs[u["problem"]], u["levels"]
+        return oracle.inner_view(oracle.eval_F(p, lv, oracle.initial_data(p, lv)), lv)
+
+    items = unit_slices(plan)
+    for (u, sl), r in zip(items, parallel(ref, items)):
+        assert rel_maxerr(out[sl], r) < 1e-12, (u, rel_maxerr(out[sl], r))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dirichlet_axis_solves(name):
+    import torch
+    probs, grid = CASES[name]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    rng = np.random.default_rng(9)
+    x = rng.uniform(-1, 1, plan.vector_len)
+    for u, sl in unit_slices(plan):
+        x[sl] = np.where(_outer_mask(probs[u["problem"]], u["levels"]), 0.0, x[sl])
+    xt = torch.tensor(x, device=DEV)
+    d = probs[0].d
+    for ax in range(d):
+        out = plan.axis_solve(ax, xt).cpu().numpy()
+        for u, sl in unit_slices(plan):
+            p, lv = probs[u["problem"]], u["levels"]
+            nudt = oracle.scheme_amfrw2().nu * p.T / 4
+            ref = oracle.inner_view(oracle.solve_axis(p, lv, ax, nudt, oracle.full_from_inner(x[sl], lv)), lv)
+            assert rel_maxerr(out[sl], ref) < max(1e-13, 4e-16 * (1 << lv[ax])), (ax, u)
+
+
+def _one_step_check(probs, grid, scheme_gpu, scheme_orc, steps=5, nsteps=1, schedule=None, tol=1e-12):
+    plan = Plan(probs, grid, steps=steps, scheme=scheme_gpu, device=DEV)
+    if schedule:
+        plan.set_schedule(**schedule)
+    plan.init()
+    plan.time_step(nsteps)
+    Y = plan.state().cpu().numpy()
+
+    def ref(item):
+        u, sl = item
+        p, lv = probs[u["problem"]], u["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / steps, nsteps, scheme=scheme_orc)
+        return oracle.inner_view(Yf, lv)
+
+    items = unit_slices(plan)
+    for (u, sl), r in zip(items, parallel(ref, items)):
+        err = rel_maxerr(Y[sl], r)
+        assert err < max(tol, 4e-16 * (1 << max(u["levels"]))), (u, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dirichlet_one_step(name):
+    probs, grid = CASES[name]
+    _one_step_check(probs, grid, S.scheme_amfrw2(), oracle.scheme_amfrw2(), nsteps=2)
+
+
+@pytest.mark.parametrize("schedule", [dict(stencil_nodes=2, fuse_axis0=1), dict(stencil_nodes=4, xcd_remap=1),
+                                      dict(resident=1)])
+def test_dirichlet_schedules(schedule):
+    probs, grid = CASES["d4_ct_mixed"]
+    plan = Plan(probs, grid, steps=4, device=DEV)
+    sc = plan.schedule()
+    if schedule.get("resident") and not sc["resident_available"]:
+        pytest.skip("grids exceed the resident size limit")
+    _one_step_check(probs, grid, S.scheme_amfrw2(), oracle.scheme_amfrw2(), nsteps=3, schedule=schedule)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_dirichlet_prices(precision, tol):
+    probs = _mixed_bc(I.draw_instances(4, seed=71, d=4))
+    grid = I.combination(5, 1)
+    plan = Plan(probs, grid, 12, precision=precision, device=DEV)
+    prices = plan.price().cpu().numpy()
+    refs = parallel(lambda p: oracle.price(p, grid, 12, nthreads=1), probs)
+    for got, ref in zip(prices, refs):
+        assert abs(got - ref) / abs(ref) < tol, (got, ref)
+    # the boundary kind changes the price (the test is not blind to it)
+    neu = dataclasses.replace(probs[0], boundary=I.NEUMANN)
+    assert abs(refs[0] - oracle.price(neu, grid, 12)) > 1e-8 * abs(refs[0])
+
+
+# ----------------------------------------------------------------------------------------------
+# Generic stage counts (eq. row-s) with the AMF W
+
+def _table(s, seed):
+    """A stage table: a = theta, q = -1, b = 1 (theta-method sweeps) for seed 0, else arbitrary."""
+    if seed == 0:
+        return [[0.5] * r for r in range(s)], [[-1.0] * r for r in range(s)], [1.0] * s
+    rng = np.random.default_rng(seed)
+    a = [list(rng.uniform(0.1, 0.9, r)) for r in range(s)]
+    q = [list(rng.uniform(-1.5, 0.5, r)) for r in range(s)]
+    b = list(rng.dirichlet(np.ones(s)))
+    return a, q, b
+
+
+@pytest.mark.parametrize("s,seed", [(1, 0), (3, 0), (3, 5), (4, 6), (6, 0)])
+@pytest.mark.parametrize("name", ["d3_ct_mixed", "d4_ct_mixed", "d2_long_axis0_dir"])
+def test_generic_stages_one_step(name, s, seed):
+    probs, grid = CASES[name]
+    a, q, b = _table(s, seed)
+    th = 0.5 if seed == 0 else 0.7
+    _one_step_check(probs, grid, S.scheme_generic(a, q, b, th, th), oracle.scheme_generic(a, q, b, th, th),
+                    nsteps=2)
+
+
+@pytest.mark.parametrize("s,seed", [(3, 0), (3, 5)])
+def test_generic_stages_fused_schedule(s, seed):
+    probs, grid = CASES["d4_ct_mixed"]
+    a, q, b = _table(s, seed)
+    _one_step_check(probs, grid, S.scheme_generic(a, q, b, 0.6, 0.6), oracle.scheme_generic(a, q, b, 0.6, 0.6),
+                    nsteps=2, schedule=dict(stencil_nodes=2, fuse_axis0=1))
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_generic_three_stage_prices(precision, tol):
+    """Prices of a 3-stage table (the theta-method with three AMF-preconditioned sweeps) through
+    the combination technique, against the oracle's generic driver."""
+    probs = I.draw_instances(2, seed=81, d=3)
+    grid = I.combination(5, 1)
+    a, q, b = _table(3, 0)
+    plan = Plan(probs, grid, 10, precision=precision, scheme=S.scheme_generic(a, q, b, 0.5, 0.5), device=DEV)
+    prices = plan.price().cpu().numpy()
+    for got, p in zip(prices, probs):
+        ref = oracle.price(p, grid, 10, scheme=oracle.scheme_generic(a, q, b, 0.5, 0.5))
+        assert abs(got - ref) / abs(ref) < tol, (got, ref)
+
+
+# ----------------------------------------------------------------------------------------------
+# W = P: theta-method + Gauss-Seidel (Section 4.2)
+
+@pytest.mark.parametrize("stages", [1, 2, 3])
+@pytest.mark.parametrize("name", ["fg2d_dir", "d2_long_axis0_dir", "d3_ragged_dir", "d3_ct_mixed",
+                                  "d4_ct_mixed", "d2_standard_ct_dir", "d6_ct_dir"])
+def test_lower_w_one_step(name, stages):
+    """Every node after two steps of the W = P method: the wavefront lower-triangular solve of each
+    unit (lines of up to 512 rows split over lanes, one workgroup per unit) against forward
+    substitution in the oracle."""
+    probs, grid = CASES[name]
+    _one_step_check(probs, grid, S.scheme_theta_gs(0.5, stages), oracle.scheme_theta_gs(0.5, stages), nsteps=2)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_lower_w_prices(precision, tol):
+    probs = I.draw_instances(3, seed=91, d=4)
+    grid = I.combination(4, 1)
+    plan = Plan(probs, grid, 16, precision=precision, scheme=S.scheme_theta_gs(0.5, 2), device=DEV)
+    prices = plan.price().cpu().numpy()
+    refs = parallel(lambda p: oracle.price(p, grid, 16, nthreads=1, scheme=oracle.scheme_theta_gs(0.5, 2)), probs)
+    for got, ref in zip(prices, refs):
+        assert abs(got - ref) / abs(ref) < tol, (got, ref)
+
+
+def test_lower_w_long_lines_and_graph():
+    """Axis-1 lines of 1024 rows (16 rows per lane) and a graph-replayed solve equal to the eager one."""
+    probs = I.workload_fg2d()["problems"]
+    grid = I.full_grid([10, 4])
+    _one_step_check(probs, grid, S.scheme_theta_gs(0.5, 2), oracle.scheme_theta_gs(0.5, 2), nsteps=1)
+    plan = Plan(probs, grid, 6, scheme=S.scheme_theta_gs(0.5, 2), device=DEV)
+    eager = plan.price().cpu().numpy()
+    plan.use_graph(True)
+    for _ in range(3):
+        assert np.array_equal(plan.price().cpu().numpy(), eager)
+
+
+# ----------------------------------------------------------------------------------------------
+# Failure signal
+
+def test_combine_checked_reports_non_finite_prices():
+    """An unstable configuration (nu far below theta, large dt) overflows; the checked combine
+    returns AMF_E_NUMERIC naming the problem, and passes on a stable plan."""
+    w = I.workload_fg2d()
+    sc = S.scheme_amfrw2(0.05)
+    plan = Plan(w["problems"], I.full_grid([8, 8]), 2, scheme=sc, device=DEV)
+    plan.solve()
+    for _ in range(60):
+        plan.time_step(2)
+    with pytest.raises(L.AmfError) as ei:
+        plan.combine_checked()
+    assert ei.value.status == L.E_NUMERIC
+    good = Plan(w["problems"], w["grid"], 10, device=DEV)
+    good.solve()
+    assert np.isfinite(good.combine_checked().cpu().numpy()).all()

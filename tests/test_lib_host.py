@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
-    assert lib.amf_abi_version() == 1
+    assert lib.amf_abi_version() == 2
 
 
 def _create(probs, grid, steps=10, prec=L.FP64, rich=0, scheme=None):
@@ -48,6 +48,22 @@ def test_scheme_coefficients():
     assert s.a[1 * 6 + 0] == 2.0 / 3.0 and s.q[1 * 6 + 0] == -4.0 / 3.0
     assert (s.b[0], s.b[1]) == (1.25, 0.75)
     assert abs(s.theta - (3 + math.sqrt(3)) / 6) < 1e-16 and s.nu == s.theta
+    assert s.w_matrix == L.W_AMF and s.struct_size == C.sizeof(L.AmfScheme)
+
+
+@pytest.mark.parametrize("stages", [1, 2, 3, 6])
+def test_theta_gauss_seidel_scheme(stages):
+    """Section 4.2: W = P, a_rj = theta, q_rj = -1, b_r = 1."""
+    s = S.scheme_theta_gs(0.5, stages)
+    assert s.stages == stages and s.w_matrix == L.W_LOWER and s.theta == 0.5
+    for r in range(stages):
+        assert s.b[r] == 1.0
+        for j in range(6):
+            assert s.a[r * 6 + j] == (0.5 if j < r else 0.0)
+            assert s.q[r * 6 + j] == (-1.0 if j < r else 0.0)
+    bad = L.AmfScheme()
+    assert L.lib().amf_scheme_theta_gs(0.0, 2, C.byref(bad)) == L.E_INVALID
+    assert L.lib().amf_scheme_theta_gs(0.5, 7, C.byref(bad)) == L.E_INVALID
 
 
 @pytest.mark.parametrize("mutate,status", [
@@ -75,8 +91,26 @@ def test_invalid_grid_and_scheme():
     assert _create([p], I.full_grid([20, 1, 1, 1]))[0] == L.E_INVALID
     assert _create([p], I.combination(5, 1), steps=0)[0] == L.E_INVALID
     sc = S.scheme_amfrw2()
-    sc.stages = 3
-    assert _create([p], I.combination(5, 1), scheme=sc)[0] == L.E_UNSUPPORTED
+    sc.stages = 7
+    assert _create([p], I.combination(5, 1), scheme=sc)[0] == L.E_INVALID
+    sc = S.scheme_amfrw2()
+    sc.w_matrix = 2
+    assert _create([p], I.combination(5, 1), scheme=sc)[0] == L.E_INVALID
+    sc = S.scheme_amfrw2()
+    sc.nu = 0.0
+    assert _create([p], I.combination(5, 1), scheme=sc)[0] == L.E_INVALID
+    for st in (1, 3, 6):                                                 # generic stage counts
+        sc = S.scheme_theta_gs(0.5, st)
+        sc.w_matrix = L.W_AMF
+        code, h = _create([p], I.combination(5, 1), scheme=sc)
+        assert code == L.OK
+        L.lib().amf_plan_destroy(h)
+    arr = (L.AmfProblem * 1)(S.problem_struct(I.draw_instances(1, seed=1, d=4)[0]))
+    arr[0].boundary = 5
+    gs = S.grid_struct(I.combination(5, 1))
+    sc = S.scheme_amfrw2()
+    h = C.c_void_p()
+    assert L.lib().amf_plan_create(arr, 1, C.byref(gs), C.byref(sc), L.FP64, 10, 0, C.byref(h)) == L.E_INVALID
     q = I.draw_instances(1, seed=1, d=3)[0]
     assert _create([p, q], I.combination(5, 1))[0] == L.E_INVALID      # mixed d
     p7 = I.draw_instances(1, seed=1, d=7)[0]
