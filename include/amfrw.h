@@ -360,6 +360,20 @@ amf_status amf_mlp_set_router(amf_mlp* mlp, const float* box_lo, const float* bo
 amf_status amf_price_or_fallback(amf_mlp* mlp, amf_plan* fallback, const float* d_x, float tol,
                                  float abs_floor, double* d_prices, int32_t* d_used_solver, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): amf_solve + amf_combine of an UNBOUND (or bound) plan in
+ * a library-owned workspace, a static device array of AMF_STATIC_WORKSPACE_BYTES per GPU that the
+ * library holds until the process ends.  The call uploads the plan's tables into that array, runs
+ * the whole solve eagerly (no graph) on `stream` and writes one FP64 price per problem to d_prices
+ * (device).  It calls no hipMalloc/hipFree and no allocating library routine.  AMF_E_INVALID when
+ * the plan needs more workspace than the array holds.  Every call on one GPU shares that GPU's
+ * array and leaves its contents behind (nothing in it is assumed to start at zero): calls that
+ * overlap on one GPU (two host threads, or two streams in flight) race and are not allowed.  A
+ * plan bound with amf_plan_bind keeps its own workspace and state untouched.  The stream must
+ * belong to the current device. */
+#define AMF_STATIC_WORKSPACE_BYTES (64u << 20)
+amf_status amf_solve_static(amf_plan* plan, double* d_prices, void* stream);
+
 /* Release host resources.  Device memory stays owned by the caller.  NULL is allowed. */
 void amf_plan_destroy(amf_plan* plan);
 

@@ -16,6 +16,7 @@ FP64, FP32 = 0, 1
 PAYOFF_CAPLET, PAYOFF_SWAPTION = 0, 1
 BC_NEUMANN, BC_DIRICHLET = 0, 1
 W_AMF, W_LOWER = 0, 1
+STATIC_WORKSPACE_BYTES = 64 << 20
 STATUS_NAMES = {0: "AMF_OK", 1: "AMF_E_INVALID", 2: "AMF_E_UNSUPPORTED", 3: "AMF_E_NOMEM",
                 4: "AMF_E_HIP", 5: "AMF_E_NUMERIC", 6: "AMF_E_STATE"}
 
@@ -124,6 +125,8 @@ def lib():
         L.amf_combine.argtypes = [vp, vp, vp]
         L.amf_combine_checked.restype = st
         L.amf_combine_checked.argtypes = [vp, vp, vp]
+        L.amf_solve_static.restype = st
+        L.amf_solve_static.argtypes = [vp, vp, vp]
         L.amf_state_read.restype = st
         L.amf_state_read.argtypes = [vp, vp, vp]
         L.amf_apply_operator.restype = st
@@ -157,4 +160,4 @@ EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_schem
             "amf_mlp_last_error", "amf_mlp_create", "amf_mlp_info_get", "amf_mlp_bind",
             "amf_mlp_set_normalization", "amf_mlp_params", "amf_mlp_grads", "amf_mlp_forward",
             "amf_mlp_backward", "amf_mlp_train_step", "amf_mlp_destroy", "amf_mlp_set_router",
-            "amf_price_or_fallback"]
+            "amf_price_or_fallback", "amf_solve_static"]

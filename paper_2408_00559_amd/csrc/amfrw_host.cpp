@@ -5,6 +5,7 @@
 #include <cstring>
 #include <exception>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -1331,6 +1332,69 @@ amf_status amf_price_or_fallback(amf_mlp* mlp, amf_plan* P, const float* d_x, fl
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     if (bad >= 0) return fail(AMF_E_NUMERIC, "non-finite price of request " + std::to_string(bad));
     return AMF_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Workspace of amf_solve_static: a file-scope device array, one copy per GPU the library runs on,
+// held until the process ends.  Host code never uses its name as an address: the device address
+// comes from hipGetSymbolAddress, once per device (with that device current), kept in g_static.
+constexpr size_t STATIC_BYTES = AMF_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void* g_static[MAX_DEVICES] = {};
+
+amf_status static_workspace(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(AMF_E_UNSUPPORTED, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress");
+        if (!ptr || ((uintptr_t)ptr & 255u)) return fail(AMF_E_HIP, "static workspace address is not 256-byte aligned");
+        g_static[dev] = ptr;
+    }
+    *out = g_static[dev];
+    return AMF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+amf_status amf_solve_static(amf_plan* P, double* d_prices, void* stream)
+{
+    if (!P || !d_prices) return fail(AMF_E_INVALID, "null argument");
+    if (P->core_bytes > STATIC_BYTES)
+        return fail(AMF_E_INVALID, "plan needs " + std::to_string(P->core_bytes) + " bytes of workspace; the static "
+                                   "workspace holds " + std::to_string(STATIC_BYTES));
+    void* ws = nullptr;
+    amf_status st = static_workspace(&ws);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // the plan's own binding (if any) is left as it was: its workspace is not touched
+    char* const saved_ws = P->ws;
+    const DevPlan saved_dev = P->dev;
+    const bool saved_bound = P->bound, saved_init = P->initialised, saved_coarse = P->have_coarse;
+    st = bind_impl(P, ws, s);                          // tables into the static workspace
+    if (!st) st = solve_body(P, s);                    // eager launches: nothing is captured
+    if (!st) {
+        P->have_coarse = P->richardson != 0;
+        st = amf_combine(P, d_prices, stream);
+    }
+    P->ws = saved_ws;                                  // kernels already hold their arguments
+    P->dev = saved_dev;
+    P->bound = saved_bound;
+    P->initialised = saved_init;
+    P->have_coarse = saved_coarse;
+    return st;
 }
 
 amf_status amf_state_read(amf_plan* P, void* d_out, void* stream)

@@ -85,6 +85,41 @@ def _stream(stream=None) -> C.c_void_p:
     return C.c_void_p(st.cuda_stream)
 
 
+class StaticPlan:
+    """An unbound plan for amf_solve_static: host tables only; each price() call runs the whole
+    solve in the library's static per-GPU workspace (no device allocation by the library or here,
+    apart from the output tensor the caller may pass in)."""
+
+    def __init__(self, problems: Sequence[Problem], grid: GridSpec, steps: int, precision: str = "fp64",
+                 richardson: bool = False, scheme: L.AmfScheme | None = None):
+        lib = L.lib()
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (L.AmfProblem * n)(*[problem_struct(p) for p in self.problems])
+        gs = grid_struct(grid)
+        sc = scheme if scheme is not None else scheme_amfrw2()
+        h = C.c_void_p()
+        L.check(lib.amf_plan_create(arr, n, C.byref(gs), C.byref(sc), L.FP64 if precision == "fp64" else L.FP32,
+                                    int(steps), 1 if richardson else 0, C.byref(h)))
+        self._h = h
+
+    def price(self, out: torch.Tensor, stream=None) -> torch.Tensor:
+        assert out.dtype == torch.float64 and out.numel() >= len(self.problems) and out.is_contiguous()
+        L.check(L.lib().amf_solve_static(self._h, C.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            L.lib().amf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Plan:
     """A bound plan: problems x component grids, the workspace on `device`, and the solve calls."""
 
