@@ -238,6 +238,10 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
  *                  produce, so no separate axis-1 sweep runs; allowed when stencil_nodes >= 2 and
  *                  256 * stencil_nodes >= the longest axis-1 line (fuse_max_axis0 reports that
  *                  line length); 0 = separate axis-1 sweep launches.
+ *   march:         streaming schedule, d <= 4 only (march_available): 1 = the time-loop operators
+ *                  run plane-tiled, one block per (grid, tile of the axes 1..d-1, range of V
+ *                  planes) walking the V axis with the tile's neighbourhood in an LDS ring of
+ *                  planes (every stencil neighbour read from LDS); excludes fuse_axis0.
  * amf_schedule_set may be called at any time between enqueued calls; AMF_E_INVALID otherwise. */
 typedef struct {
     uint32_t struct_size;
@@ -248,6 +252,8 @@ typedef struct {
     int32_t resident_available;  /* read-only: filled by amf_schedule_get */
     int32_t fuse_axis0;
     int32_t fuse_max_axis0;      /* read-only: longest axis-1 line M_1 of the plan */
+    int32_t march;
+    int32_t march_available;     /* read-only: filled by amf_schedule_get */
 } amf_schedule;
 
 amf_status amf_schedule_get(const amf_plan* plan, amf_schedule* out);

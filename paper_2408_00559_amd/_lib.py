@@ -52,7 +52,8 @@ class AmfPlanInfo(C.Structure):
 class AmfSchedule(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("stencil_nodes", C.c_int32), ("xcd_remap", C.c_int32),
                 ("max_stencil_nodes", C.c_int32), ("resident", C.c_int32), ("resident_available", C.c_int32),
-                ("fuse_axis0", C.c_int32), ("fuse_max_axis0", C.c_int32)]
+                ("fuse_axis0", C.c_int32), ("fuse_max_axis0", C.c_int32), ("march", C.c_int32),
+                ("march_available", C.c_int32)]
 
 
 class AmfKernelStat(C.Structure):

@@ -28,12 +28,15 @@ def signature(plan) -> str:
 def candidates(plan):
     sc = plan.schedule()
     nodes = [r for r in (1, 2, 4, 8) if r <= sc["max_stencil_nodes"]]
-    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=0)
+    out = [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=0, march=0)
            for r, x in itertools.product(nodes, (0, 1, 2))]
-    out += [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=1)
+    out += [dict(stencil_nodes=r, xcd_remap=x, resident=0, fuse_axis0=1, march=0)
             for r, x in itertools.product(nodes, (0, 1)) if plan.fuse_allowed(r)]
+    if sc["march_available"]:
+        out += [dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=x, resident=0, fuse_axis0=0, march=1)
+                for x in (0, 1, 2)]
     if sc["resident_available"]:
-        out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1, fuse_axis0=0))
+        out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1, fuse_axis0=0, march=0))
     return out
 
 

@@ -69,6 +69,10 @@ struct amf_plan {
     int64_t total = 0;                     // elements per grid vector (with alignment padding)
     int64_t inner = 0;                     // inner points over all units
 
+    // marching operator (d <= 4): blocks and the largest plane slot
+    std::vector<MarchBlk> march_blk;
+    int march_lp = 0, march = 0;
+    size_t off_march = 0;
     // W = P solves: hyperplanes of axis-0 lines per unit (built only for w_matrix = AMF_W_LOWER)
     std::vector<int32_t> gs_unit_plane0, gs_lines;
     std::vector<int64_t> gs_plane_line0;
@@ -704,6 +708,20 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             }
         }
 
+        // marching operator blocks (d <= 4)
+        if (d <= 4) {
+            std::vector<int8_t> lvs((size_t)P->n_units * MAXD);
+            for (int u = 0; u < P->n_units; ++u)
+                for (int i = 0; i < MAXD; ++i) lvs[(size_t)u * MAXD + i] = P->units[u].lv[i];
+            march_blocks(d, P->n_units, lvs.data(), MAXD, (int)P->elem, P->march_blk);
+            if ((int64_t)P->march_blk.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
+            for (const MarchBlk& B : P->march_blk) {
+                int lp = 1;
+                for (int k = 0; k < d - 1; ++k) lp *= (1 << B.lt[k]) + 2;
+                P->march_lp = std::max(P->march_lp, lp);
+            }
+        }
+
         // workspace layout
         size_t o = 0;
         const size_t vb = align_up((size_t)P->total * P->elem, 256);
@@ -727,6 +745,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             P->off_axl[ax] = take(P->ax_line_off[ax].size() * sizeof(int64_t));
             P->off_axb[ax] = take(P->ax_blk[ax].size() * sizeof(SweepBlk));
         }
+        P->off_march = take(P->march_blk.size() * sizeof(MarchBlk));
         P->off_gsu = take(P->gs_unit_plane0.size() * sizeof(int32_t));
         P->off_gsp = take(P->gs_plane_line0.size() * sizeof(int64_t));
         P->off_gsl = take(P->gs_lines.size() * sizeof(int32_t));
@@ -814,6 +833,7 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
         if ((st = upload(P->ws + P->off_axl[ax], P->ax_line_off[ax].data(), P->ax_line_off[ax].size() * 8, s))) return st;
         if ((st = upload(P->ws + P->off_axb[ax], P->ax_blk[ax].data(), P->ax_blk[ax].size() * sizeof(SweepBlk), s))) return st;
     }
+    if ((st = upload(P->ws + P->off_march, P->march_blk.data(), P->march_blk.size() * sizeof(MarchBlk), s))) return st;
     if ((st = upload(P->ws + P->off_gsu, P->gs_unit_plane0.data(), P->gs_unit_plane0.size() * 4, s))) return st;
     if ((st = upload(P->ws + P->off_gsp, P->gs_plane_line0.data(), P->gs_plane_line0.size() * 8, s))) return st;
     if ((st = upload(P->ws + P->off_gsl, P->gs_lines.data(), P->gs_lines.size() * 4, s))) return st;
@@ -854,6 +874,10 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
     D.gs_unit_plane0 = gs ? (const int32_t*)(P->ws + P->off_gsu) : nullptr;
     D.gs_plane_line0 = gs ? (const int64_t*)(P->ws + P->off_gsp) : nullptr;
     D.gs_lines = gs ? (const int32_t*)(P->ws + P->off_gsl) : nullptr;
+    D.march = P->march;
+    D.march_blk = P->march_blk.empty() ? nullptr : (const MarchBlk*)(P->ws + P->off_march);
+    D.n_march = (int64_t)P->march_blk.size();
+    D.march_lds = MARCH_SLOTS * P->march_lp * (int)P->elem;
     P->bound = true;
     return AMF_OK;
 }
@@ -1451,6 +1475,8 @@ amf_status amf_schedule_get(const amf_plan* P, amf_schedule* out)
     out->resident_available = P->res_ok ? 1 : 0;
     out->fuse_axis0 = P->fuse0;
     out->fuse_max_axis0 = P->max_m0;
+    out->march = P->march;
+    out->march_available = P->march_blk.empty() ? 0 : 1;
     return AMF_OK;
 }
 
@@ -1468,8 +1494,14 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
         return fail(AMF_E_INVALID, "fuse_axis0 applies to the AMF W only");
     if (sc->fuse_axis0 && (r < 2 || NODE_BLOCK * r < P->max_m0))
         return fail(AMF_E_INVALID, "fuse_axis0 needs stencil_nodes >= 2 and 256 * stencil_nodes >= the longest axis-1 line");
-    if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident || sc->fuse_axis0 != P->fuse0)
+    if (sc->march != 0 && sc->march != 1) return fail(AMF_E_INVALID, "march must be 0 or 1");
+    if (sc->march && P->march_blk.empty()) return fail(AMF_E_INVALID, "the marching operator needs d <= 4");
+    if (sc->march && sc->fuse_axis0) return fail(AMF_E_INVALID, "the marching operator does not fuse the axis-1 solve");
+    if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident || sc->fuse_axis0 != P->fuse0 ||
+        sc->march != P->march)
         P->drop_graph();
+    P->march = sc->march;
+    P->dev.march = sc->march;
     P->resident = sc->resident;
     P->fuse0 = sc->fuse_axis0;
     P->stencil_r = r;

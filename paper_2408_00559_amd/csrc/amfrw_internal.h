@@ -5,10 +5,11 @@
 #include <cstdint>
 
 #include "amfrw.h"
+#include "amfrw_consts.h"
+#include "amfrw_march.h"
 
 namespace amf {
 
-constexpr int MAXD = 6;            // kernels are instantiated for d = 2..6
 constexpr int NODE_BLOCK = 256;    // threads per block of the per-node kernels
 constexpr int LINE_BLOCK = 256;    // threads per block of the sweep kernels
 constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
@@ -45,13 +46,6 @@ constexpr int CONTIG_REG_LM = 4;
 // short lines are not held to the register allocation of the long-line code.
 constexpr int SHORT_LM = 4;
 
-// Per-problem constants in the plan precision, at ProbDev::cst inside the table array.
-enum CstIndex : int {
-    CST_RHO = 0,                     // rho_ik between rates i, k (MAXD x MAXD, row-major)
-    CST_SPHI = MAXD * MAXD,          // sigma * phi_i
-    CST_RUN = CST_SPHI + MAXD,       // per run (coarse, fine): dt, nu dt, theta dt
-    CST_SIZE = CST_RUN + 6
-};
 
 // One unit = one (problem, component grid) pair.  Inner nodes only, axis 0 fastest.
 struct alignas(16) UnitDev {
@@ -123,17 +117,13 @@ struct DevPlan {
     const int32_t* gs_unit_plane0;
     const int64_t* gs_plane_line0;
     const int32_t* gs_lines;
+    // marching (plane-tiled) operator, d <= 4: blocks and dynamic LDS bytes per block
+    int march;                         // 1: the time-loop operators use the marching kernel
+    const MarchBlk* march_blk;
+    int64_t n_march;
+    int march_lds;
 };
 
-// Stencil operation selector.  Solution vectors are stored as W = Y - g (zero on every lower face);
-// cG = F(g) is computed once per solve with the payoff on the lower faces.
-enum StencilOp : int {
-    OP_F_PAYOFF = 0,   // W = s F(X0), lower faces = payoff
-    OP_F_ZERO = 1,     // W = s F(X0), lower faces = 0
-    OP_STAGE1 = 2,     // W = s (F(X0) + cG)                  (first stage, X0 = W_n)
-    OP_STAGE2 = 3,     // W = s (F(X0 + a X1) + cG) + q X2    (later stages; AMFR-W2: X1 = X2 = K_1)
-    OP_REFINE = 4      // W = 2 W - X0 + s F(X0)              (refinement of eq amfrw)
-};
 
 struct StencilArgs {
     const void* X0;

@@ -534,6 +534,72 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
 }
 
 // ------------------------------------------------------------------------------------------------
+// The time-loop operator in its plane-tiled form (amfrw_march.h): one block per (unit, tile of the
+// plane axes, range of V planes); the neighbour values come from a ring of LDS plane slots.
+template <typename T>
+struct GpuMem {
+    T* lds;
+    __device__ __forceinline__ T ld(const T* p, int64_t i) const { return p[i]; }
+    __device__ __forceinline__ T tab(const T* p, int i) const { return p[i]; }
+    __device__ __forceinline__ T sr(int i) const { return lds[i]; }
+    __device__ __forceinline__ void sw(int i, T v) const { lds[i] = v; }
+};
+
+template <typename T, int D, int OP>
+__global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs A)
+{
+    static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    GpuMem<T> m{(T*)march_smem};
+    const int64_t bi = xcd_block(blockIdx.x, gridDim.x, P.xcd != 0);
+    const MarchBlk B = P.march_blk[bi];
+    const UnitDev& U = P.units[B.unit];
+    MarchGeo<D> G;
+    march_geo<D>(U.lv, U.off, B, G);
+    const ProbDev& PR = P.probs[U.prob];
+    const T* tab = (const T*)P.tab;
+    const T* cst = tab + PR.cst;
+    const int tid = threadIdx.x;
+    MarchThr<T, D> t;
+    march_thread<T, D>(G, tid, t);
+    march_coefs<T, D>(G, U.tab, tab, cst, t, m);
+    const T* X0 = (const T*)A.X0;
+    const T* X1 = (const T*)A.X1;
+    const T av = (T)A.a;
+    const T* tV = tab + U.tab[D - 1];
+    const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
+    const int MV = G.M[D - 1];
+    const int last = min(MV, G.v0 + G.vn + 1);            // last plane the block reads
+    // planes v0 .. v0 + 2 (plane 0 is the lower face: zeros)
+    for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
+        march_fetch<T, D, OP>(G, tid, p, X0, X1, av, t, m);
+        march_stash<T, D>(G, tid, p, t, m);
+    }
+    __syncthreads();
+    const T* cG = (const T*)A.cG;
+    const T* X2 = A.X2 ? (const T*)A.X2 : X1;
+    T* W = (T*)A.W;
+    for (int s = 1; s <= G.vn; ++s) {
+        const int jv = G.v0 + s;
+        const int pn = jv + 2;
+        const bool more = pn <= last;                         // block-uniform
+        if (more) march_fetch<T, D, OP>(G, tid, pn, X0, X1, av, t, m);
+        if (t.active) {
+            T c0;
+            const T F = march_F<T, D>(G, t, jv, tV, cst, PR.dirichlet, c0, m);
+            const int64_t g = march_index<D>(G, t, jv);
+            T o;
+            if constexpr (OP == OP_STAGE1) o = sc * (F + cG[g]);
+            else if constexpr (OP == OP_STAGE2) o = sc * (F + cG[g]) + (T)A.q * X2[g];
+            else o = T(2) * W[g] - c0 + sc * F;
+            W[g] = o;
+        }
+        if (more) march_stash<T, D>(G, tid, pn, t, m);   // the slot of plane jv - 2: read last step
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 // Directional solves (I - nu dt A_i) x = G (Lemma lema:ls): rows r = 0..M-1 with delta_r =
 // d_i / h_i^2, diagonal 1 + 2 nu dt delta_r, super-diagonal -nu dt delta_r (none in the last row),
 // sub-diagonal -nu dt delta_r (none in the first row, doubled in the last row: Neumann ghost).
@@ -1553,9 +1619,28 @@ static hipError_t stencil_vec(const DevPlan& P, int op, const StencilArgs& a, hi
 }
 
 template <typename T, int D>
+static hipError_t march_td(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
+{
+    if constexpr (D > 4) {
+        return hipErrorInvalidValue;
+    } else {
+        dim3 g((unsigned)P.n_march), b(MARCH_THREADS);
+        const size_t shm = (size_t)P.march_lds;
+        switch (op) {
+        case OP_STAGE1: hipLaunchKernelGGL((k_march<T, D, OP_STAGE1>), g, b, shm, s, P, a); break;
+        case OP_STAGE2: hipLaunchKernelGGL((k_march<T, D, OP_STAGE2>), g, b, shm, s, P, a); break;
+        case OP_REFINE: hipLaunchKernelGGL((k_march<T, D, OP_REFINE>), g, b, shm, s, P, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+}
+
+template <typename T, int D>
 static hipError_t stencil_td(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
     const bool hot = op == OP_STAGE1 || op == OP_STAGE2 || op == OP_REFINE;
+    if (hot && P.march && a.S == nullptr && P.n_march > 0) return march_td<T, D>(P, op, a, s);
     if (hot && P.stencil_r == 8) return stencil_vec<T, D, 8>(P, op, a, s);
     if (hot && P.stencil_r == 4) return stencil_vec<T, D, 4>(P, op, a, s);
     if (hot && P.stencil_r == 2) return stencil_vec<T, D, 2>(P, op, a, s);

@@ -241,24 +241,26 @@ class Plan:
         return dict(stencil_nodes=sc.stencil_nodes, xcd_remap=sc.xcd_remap,
                     max_stencil_nodes=sc.max_stencil_nodes, resident=sc.resident,
                     resident_available=sc.resident_available, fuse_axis0=sc.fuse_axis0,
-                    fuse_max_axis0=sc.fuse_max_axis0)
+                    fuse_max_axis0=sc.fuse_max_axis0, march=sc.march, march_available=sc.march_available)
 
     def fuse_allowed(self, stencil_nodes: int) -> bool:
         """Whether the operator launches can also solve axis 0 at this many nodes per thread."""
         return stencil_nodes >= 2 and 256 * stencil_nodes >= self.schedule()["fuse_max_axis0"]
 
     def set_schedule(self, stencil_nodes: int | None = None, xcd_remap: int | None = None,
-                     resident: int | None = None, fuse_axis0: int | None = None):
+                     resident: int | None = None, fuse_axis0: int | None = None, march: int | None = None):
         """Change launch knobs; unspecified ones keep their value (fuse_axis0 is switched off when
-        a new stencil_nodes does not allow it and it was not given)."""
+        a new stencil_nodes does not allow it, or the marching operator is chosen, and it was not
+        given)."""
         cur = self.schedule()
         sc = L.AmfSchedule()
         sc.struct_size = C.sizeof(L.AmfSchedule)
         sc.stencil_nodes = cur["stencil_nodes"] if stencil_nodes is None else int(stencil_nodes)
         sc.xcd_remap = cur["xcd_remap"] if xcd_remap is None else int(xcd_remap)
         sc.resident = cur["resident"] if resident is None else int(resident)
+        sc.march = cur["march"] if march is None else int(march)
         if fuse_axis0 is None:
-            sc.fuse_axis0 = cur["fuse_axis0"] if self.fuse_allowed(sc.stencil_nodes) else 0
+            sc.fuse_axis0 = cur["fuse_axis0"] if self.fuse_allowed(sc.stencil_nodes) and not sc.march else 0
         else:
             sc.fuse_axis0 = int(fuse_axis0)
         L.check(L.lib().amf_schedule_set(self._h, C.byref(sc)))

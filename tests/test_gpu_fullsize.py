@@ -8,7 +8,11 @@
 * 512 seeded d = 4 instances (n = 6, psi = 1): the first 16 prices against the oracle's stored
   values, FP64 and FP32, in the serving configuration (autotuned schedule, graph replay).
 * d = 6, n = 8, psi = 1 with the Richardson pair (2,975 grids): u_l(x_eval) of sampled grids after
-  the solve against the oracle's stored values (tests/golden/ct6_n8_psi1_sampled_fp64.json).
+  the full 200 + 400 steps against the oracle's stored values
+  (tests/golden/ct6_n8_psi1_sampled_fp64.json); and EVERY grid and the Richardson price over a
+  shortened horizon at the workload's step sizes (8 + 16 steps of dt = T/200 and dt/2; the full
+  horizon over all grids costs the oracle about 11 CPU-hours) against
+  tests/golden/ct6_n8_psi1_short_all_fp64.json.
 """
 import json
 import os
@@ -142,3 +146,31 @@ def test_ct6_full_size_sampled_grids(precision, tol):
     for lv, ref in zip(g["unit_levels"], g["unit_values"]):
         got = vals[index[tuple(lv)]]
         assert abs(got - ref) / scale < tol, (lv, got, ref)
+
+
+CT6ALL = os.path.join(HERE, "golden", "ct6_n8_psi1_short_all_fp64.json")
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
+def test_ct6_every_grid_short_horizon(precision, tol):
+    """Every one of the 2,975 d = 6 grids and the Richardson-extrapolated price, in the benchmark's
+    configuration (autotuned schedule, graph replay), with the workload's problem, grids and step
+    sizes over 8 coarse + 16 fine steps."""
+    g = _golden(CT6ALL)
+    w = I.workload_ct6()
+    p = w["problems"][0]
+    p.T = p.T * g["steps"] / w["steps"]
+    assert abs(p.T - g["maturity"]) < 1e-15
+    plan = Plan([p], w["grid"], g["steps"], precision=precision, richardson=True, device=DEV)
+    autotune.tune(plan, steps=1, reps=1, use_cache=False)
+    plan.use_graph(True)
+    plan.solve()
+    price = plan.combine().item()
+    assert abs(price - g["price"]) / abs(g["price"]) < tol, (price, g["price"], plan.schedule())
+    vals = plan.unit_values().cpu().numpy()
+    units = plan.units()
+    assert len(units) == len(g["unit_levels"]) == 2975
+    index = {tuple(lv): k for k, lv in enumerate(g["unit_levels"])}
+    ref = np.array([g["unit_values_fine"][index[tuple(u["levels"])]] for u in units])
+    scale = np.max(np.abs(ref))
+    assert np.max(np.abs(vals - ref)) / scale < tol, np.max(np.abs(vals - ref)) / scale

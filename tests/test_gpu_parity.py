@@ -257,6 +257,38 @@ def test_schedules_agree(name):
                 assert rel_maxerr(Y[sl], rr) < 1e-12, (r, x, u)
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("name", ["fg2d", "long_rate_axis", "long_v_axis", "very_long_v_axis", "res_one_line",
+                                  "d3_full_ragged", "d2_standard_ct", "d3_ct", "d4_ct"])
+def test_march_schedule(name, precision, tol):
+    """The plane-tiled operator (LDS ring of V planes) with the separate axis-1 solves: two steps,
+    every node of every unit against the oracle, with and without the XCD remap."""
+    probs, grid = CASES[name]
+    steps = 5
+    plan = Plan(probs, grid, steps=steps, precision=precision, device=DEV)
+    if not plan.schedule()["march_available"]:
+        pytest.skip("d > 4")
+    items = unit_slices(plan)
+
+    def ref(item):
+        u, sl = item
+        p = probs[u["problem"]]
+        lv = u["levels"]
+        Yf = oracle.initial_data(p, lv)
+        oracle.advance(p, lv, Yf, p.T / steps, 2)
+        return oracle.inner_view(Yf, lv)
+
+    refs = parallel(ref, items)
+    for x in (0, 1):
+        plan.set_schedule(march=1, fuse_axis0=0, resident=0, xcd_remap=x)
+        plan.init()
+        plan.time_step(2)
+        Y = plan.state().cpu().numpy().astype(np.float64)
+        for (u, sl), rr in zip(items, refs):
+            err = rel_maxerr(Y[sl], rr)
+            assert err < max(tol, (4e-16 if precision == "fp64" else 2e-7) * (1 << max(u["levels"]))), (x, u, err)
+
+
 def test_autotune_picks_admissible_schedule(tmp_path, monkeypatch):
     from paper_2408_00559_amd import autotune
     monkeypatch.setenv("AMF_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))

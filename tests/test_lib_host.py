@@ -204,6 +204,17 @@ def test_schedule_validation():
     assert _set(h, stencil_nodes=8, fuse_axis0=1, xcd_remap=2) == L.OK
     assert _sched(h).fuse_axis0 == 1
     assert _set(h, stencil_nodes=1, fuse_axis0=1) == L.E_INVALID
+    assert _sched(h).march_available == 1
+    assert _set(h, stencil_nodes=4, fuse_axis0=1, march=1) == L.E_INVALID   # march does not fuse
+    assert _set(h, stencil_nodes=4, fuse_axis0=0, march=2) == L.E_INVALID
+    assert _set(h, stencil_nodes=4, fuse_axis0=0, march=1) == L.OK
+    assert _sched(h).march == 1
+    L.lib().amf_plan_destroy(h)
+    # the marching operator is built for d <= 4 only
+    p6 = I.draw_instances(1, seed=9, d=6)[0]
+    st, h = _create([p6], I.combination(5, 1))
+    assert _sched(h).march_available == 0
+    assert _set(h, stencil_nodes=1, march=1) == L.E_INVALID
     L.lib().amf_plan_destroy(h)
     # a plan whose smallest axis-0 line has 2 nodes allows at most 2 nodes per thread
     p = I.draw_instances(1, seed=9, d=3)[0]
