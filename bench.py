@@ -244,6 +244,43 @@ def run_serving(torch, Plan, batches=200):
     return out
 
 
+def run_fg2d(torch, Plan, reps=200):
+    """The d = 2 full grid 65 x 65 (FP64, 50 AMFR-W2 steps, one caplet): the whole solve replayed as
+    a hipGraph; a 32 KiB state, so the time is launch latency, not bandwidth.  The error is against
+    the oracle's stored price (tests/golden/fg2d_65x65_fp64.json)."""
+    import numpy as np
+
+    from paper_2408_00559_amd import autotune
+    from paper_2408_00559_amd import inputs as I
+
+    w = I.workload_fg2d()
+    plan = Plan(w["problems"], w["grid"], w["steps"], precision="fp64", device="cuda:0")
+    tuned = autotune.tune(plan, steps=2, reps=1)
+    plan.use_graph(True)
+    pr = torch.empty(1, dtype=torch.float64, device="cuda:0")
+    plan.solve()
+    plan.combine(pr)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        plan.solve()
+        plan.combine(pr)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+    lat = np.array(lat)
+    price = float(pr.item())
+    golden = os.path.join(ROOT, "tests", "golden", "fg2d_65x65_fp64.json")
+    ref = json.load(open(golden))["price"] if os.path.exists(golden) else None
+    out = {"workload": w["name"], "time_steps": w["steps"], "inner_points": plan.inner_points,
+           "sec_per_solve_p50": float(np.median(lat)), "sec_per_solve_min": float(lat.min()),
+           "stage_updates_per_s": plan.stage_updates / float(np.median(lat)), "price": price,
+           "oracle_price": ref, "rel_err_vs_oracle": abs(price - ref) / abs(ref) if ref else None,
+           "schedule": plan.schedule(), "autotune_cached": tuned.get("cached")}
+    del plan
+    return out
+
+
 def run_ct6(torch, Plan):
     """d = 6 (5 rates + V), modified combination n = 8, psi = 1 (2975 component grids): FP32
     stencil and sweeps with FP64 combination, fourth order in time by Richardson extrapolation of
@@ -392,7 +429,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-ct6", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--only", choices=["serving", "ct6", "surrogate"], default=None,
+    ap.add_argument("--only", choices=["serving", "ct6", "surrogate", "fg2d"], default=None,
                     help="run one secondary section alone and print its JSON (profiling runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/hbm_traffic_ct4.json from two rocprofv3 --pmc runs")
@@ -415,7 +452,7 @@ def main():
     from paper_2408_00559_amd.solver import Plan
 
     if args.only:
-        run = {"serving": run_serving, "ct6": run_ct6, "surrogate": run_surrogate}[args.only]
+        run = {"serving": run_serving, "ct6": run_ct6, "surrogate": run_surrogate, "fg2d": run_fg2d}[args.only]
         print(json.dumps({args.only: run(torch, Plan)}), flush=True)
         return
     w = I.workload_ct4()
@@ -468,6 +505,7 @@ def main():
                        "rel_err_against": "oracle" if ref else "fp64 GPU",
                        "roofline": f32["roofline"], "kernels": f32["kernels"],
                        "schedule": f32["schedule"], "autotune": f32["autotune"]}
+    res["fg2d_65x65"] = run_fg2d(torch, Plan)
     if not args.no_serving:
         res["serving_batch4"] = run_serving(torch, Plan)
     if not args.no_ct6:

@@ -4,6 +4,7 @@ Calls only the CPU oracle (oracle/) and the input definitions (paper_2408_00559_
 Usage:  python tests/golden/make_golden.py ct4 [threads]      (d=4, n=7, psi=3, 100 steps, FP64)
         python tests/golden/make_golden.py batch4 [threads]   (first 16 of the 512 seeded instances)
         python tests/golden/make_golden.py ct6 [threads]      (d=6, n=8, psi=1: sampled grids, 400 steps)
+        python tests/golden/make_golden.py fg2d                (d=2 full grid 65x65, 50 steps, FP64)
         python tests/golden/make_golden.py ct6all [threads]   (d=6, n=8, psi=1: every grid, both
                                                                Richardson runs, 8 + 16 steps at the
                                                                workload's dt)
@@ -86,6 +87,17 @@ def run_ct6(threads):
     _dump(out, "ct6_n8_psi1_sampled_fp64.json")
 
 
+def run_fg2d(threads):
+    w = I.workload_fg2d()
+    p = w["problems"][0]
+    t = time.time()
+    price = oracle.price(p, w["grid"], w["steps"], nthreads=1)
+    out = dict(workload=w["name"], steps=w["steps"], levels=w["grid"].levels, price=price,
+               oracle_seconds=time.time() - t, threads=1,
+               note="FP64 CPU oracle, written by tests/golden/make_golden.py")
+    _dump(out, "fg2d_65x65_fp64.json")
+
+
 CT6_SHORT_STEPS = 8
 
 
@@ -126,4 +138,4 @@ if __name__ == "__main__":
         reformat(sys.argv[2])
         sys.exit(0)
     threads = int(sys.argv[2]) if len(sys.argv) > 2 else 0
-    {"ct4": run_ct4, "batch4": run_batch4, "ct6": run_ct6, "ct6all": run_ct6all}[which](threads)
+    {"ct4": run_ct4, "batch4": run_batch4, "ct6": run_ct6, "ct6all": run_ct6all, "fg2d": run_fg2d}[which](threads)
