@@ -6,6 +6,7 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libamfrw.so")
+ABI_VERSION = 2                       # AMF_ABI_VERSION of include/amfrw.h
 
 MAX_D = 8
 MAX_STAGES = 6

@@ -7,6 +7,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <stdexcept>
 #include <string>
 #include <thread>
 #include <vector>
@@ -70,9 +71,9 @@ struct amf_plan {
     int64_t inner = 0;                     // inner points over all units
 
     // marching operator (d <= 4): blocks and the largest plane slot
-    std::vector<MarchBlk> march_blk;
+    std::vector<MarchBlk> march_blk, march_blk_x;
     int march_lp = 0, march = 0;
-    size_t off_march = 0;
+    size_t off_march = 0, off_march_x = 0;
     // W = P solves: hyperplanes of axis-0 lines per unit (built only for w_matrix = AMF_W_LOWER)
     std::vector<int32_t> gs_unit_plane0, gs_lines;
     std::vector<int64_t> gs_plane_line0;
@@ -716,10 +717,13 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             march_blocks(d, P->n_units, lvs.data(), MAXD, (int)P->elem, P->march_blk);
             if ((int64_t)P->march_blk.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
             for (const MarchBlk& B : P->march_blk) {
-                int lp = 1;
-                for (int k = 0; k < d - 1; ++k) lp *= (1 << B.lt[k]) + 2;
-                P->march_lp = std::max(P->march_lp, lp);
+                const int lt[3] = {B.lt[0], B.lt[1], B.lt[2]};
+                const int slot = march_slot_elems(d, lt, B.h0);
+                if (slot > MARCH_MAX_PLANE) throw std::logic_error("marching tile larger than its LDS slot");
+                P->march_lp = std::max(P->march_lp, slot);
             }
+            march_order_xcd(P->march_blk, NXCD, P->march_blk_x);
+            if ((int64_t)P->march_blk_x.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
         }
 
         // workspace layout
@@ -746,6 +750,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             P->off_axb[ax] = take(P->ax_blk[ax].size() * sizeof(SweepBlk));
         }
         P->off_march = take(P->march_blk.size() * sizeof(MarchBlk));
+        P->off_march_x = take(P->march_blk_x.size() * sizeof(MarchBlk));
         P->off_gsu = take(P->gs_unit_plane0.size() * sizeof(int32_t));
         P->off_gsp = take(P->gs_plane_line0.size() * sizeof(int64_t));
         P->off_gsl = take(P->gs_lines.size() * sizeof(int32_t));
@@ -834,6 +839,8 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
         if ((st = upload(P->ws + P->off_axb[ax], P->ax_blk[ax].data(), P->ax_blk[ax].size() * sizeof(SweepBlk), s))) return st;
     }
     if ((st = upload(P->ws + P->off_march, P->march_blk.data(), P->march_blk.size() * sizeof(MarchBlk), s))) return st;
+    if ((st = upload(P->ws + P->off_march_x, P->march_blk_x.data(), P->march_blk_x.size() * sizeof(MarchBlk), s)))
+        return st;
     if ((st = upload(P->ws + P->off_gsu, P->gs_unit_plane0.data(), P->gs_unit_plane0.size() * 4, s))) return st;
     if ((st = upload(P->ws + P->off_gsp, P->gs_plane_line0.data(), P->gs_plane_line0.size() * 8, s))) return st;
     if ((st = upload(P->ws + P->off_gsl, P->gs_lines.data(), P->gs_lines.size() * 4, s))) return st;
@@ -876,7 +883,9 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
     D.gs_lines = gs ? (const int32_t*)(P->ws + P->off_gsl) : nullptr;
     D.march = P->march;
     D.march_blk = P->march_blk.empty() ? nullptr : (const MarchBlk*)(P->ws + P->off_march);
+    D.march_blk_x = P->march_blk_x.empty() ? nullptr : (const MarchBlk*)(P->ws + P->off_march_x);
     D.n_march = (int64_t)P->march_blk.size();
+    D.n_march_x = (int64_t)P->march_blk_x.size();
     D.march_lds = MARCH_SLOTS * P->march_lp * (int)P->elem;
     P->bound = true;
     return AMF_OK;

@@ -119,8 +119,9 @@ struct DevPlan {
     const int32_t* gs_lines;
     // marching (plane-tiled) operator, d <= 4: blocks and dynamic LDS bytes per block
     int march;                         // 1: the time-loop operators use the marching kernel
-    const MarchBlk* march_blk;
-    int64_t n_march;
+    const MarchBlk* march_blk;         // unit by unit
+    const MarchBlk* march_blk_x;       // grouped per XCD (used when xcd != 0)
+    int64_t n_march, n_march_x;
     int march_lds;
 };
 

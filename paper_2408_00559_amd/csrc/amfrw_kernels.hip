@@ -545,14 +545,26 @@ struct GpuMem {
     __device__ __forceinline__ void sw(int i, T v) const { lds[i] = v; }
 };
 
-template <typename T, int D, int OP>
+// The plane pipeline: DEEP keeps two planes in flight (plane j_V + 3 is loaded while plane j_V is
+// computed, plane j_V + 2 written to its slot at the top of the step), else one (plane j_V + 2 is
+// loaded at the top of the step and written to its slot after the compute).  Stage 1 and the
+// refinement also load the next node's stage values one plane ahead; stage 2, which needs two
+// values per node, loads them where they are used.
+template <typename T, int OP>
+constexpr bool march_deep()
+{
+    return false;
+}
+
+template <typename T, int D, int OP, bool DEEP>
 __global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs A)
 {
     static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
+    constexpr bool AHEAD = OP != OP_STAGE2;
     extern __shared__ __align__(16) unsigned char march_smem[];
     GpuMem<T> m{(T*)march_smem};
-    const int64_t bi = xcd_block(blockIdx.x, gridDim.x, P.xcd != 0);
-    const MarchBlk B = P.march_blk[bi];
+    const MarchBlk B = (P.xcd ? P.march_blk_x : P.march_blk)[blockIdx.x];
+    if (B.vn == 0) return;                                  // padding of the XCD-ordered table
     const UnitDev& U = P.units[B.unit];
     MarchGeo<D> G;
     march_geo<D>(U.lv, U.off, B, G);
@@ -563,38 +575,69 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs 
     MarchThr<T, D> t;
     march_thread<T, D>(G, tid, t);
     march_coefs<T, D>(G, U.tab, tab, cst, t, m);
+    march_face<T, D>(PR.dirichlet, t);
+    march_pads<T, D>(G, tid, m);
     const T* X0 = (const T*)A.X0;
     const T* X1 = (const T*)A.X1;
     const T av = (T)A.a;
     const T* tV = tab + U.tab[D - 1];
     const T sc = A.scale_sel < 0 ? (T)A.scale : cst[A.scale_sel];
+    const T qv = (T)A.q;
     const int MV = G.M[D - 1];
+    const T tdV = tV[MV];
     const int last = min(MV, G.v0 + G.vn + 1);            // last plane the block reads
-    // planes v0 .. v0 + 2 (plane 0 is the lower face: zeros)
-    for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
-        march_fetch<T, D, OP>(G, tid, p, X0, X1, av, t, m);
-        march_stash<T, D>(G, tid, p, t, m);
-    }
-    __syncthreads();
     const T* cG = (const T*)A.cG;
     const T* X2 = A.X2 ? (const T*)A.X2 : X1;
     T* W = (T*)A.W;
+    const bool act = t.active;
+    // the values the stage combination needs at this thread's node of plane jv
+    auto centre = [&](int jv, T& e0, T& e1) {
+        const int64_t g = act ? march_index<D>(G, t, jv) : G.off;
+        if constexpr (OP == OP_REFINE) {
+            e0 = W[g];                                          // K^(0)
+            e1 = T(0);
+        } else {
+            e0 = cG[g];
+            e1 = OP == OP_STAGE2 ? X2[g] : T(0);
+        }
+    };
+    // planes v0 .. v0 + 2 into their slots (plane 0 is the lower face: zeros)
+    for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
+        march_fetch<T, D, OP>(G, p, X0, X1, av, t, m);
+        march_stash<T, D>(G, tid, p, t, m);
+    }
+    if (DEEP && G.v0 + 3 <= last) march_fetch<T, D, OP>(G, G.v0 + 3, X0, X1, av, t, m);
+    T e0 = T(0), e1 = T(0);
+    if (AHEAD) centre(G.v0 + 1, e0, e1);
+    __syncthreads();
     for (int s = 1; s <= G.vn; ++s) {
         const int jv = G.v0 + s;
-        const int pn = jv + 2;
-        const bool more = pn <= last;                         // block-uniform
-        if (more) march_fetch<T, D, OP>(G, tid, pn, X0, X1, av, t, m);
-        if (t.active) {
+        // the next plane goes into the slot of plane jv - 2, which the previous step read
+        if (DEEP) {
+            if (jv + 2 <= last) march_stash<T, D>(G, tid, jv + 2, t, m);
+            if (jv + 3 <= last) march_fetch<T, D, OP>(G, jv + 3, X0, X1, av, t, m);
+        } else if (jv + 2 <= last) {
+            march_fetch<T, D, OP>(G, jv + 2, X0, X1, av, t, m);
+        }
+        T n0 = T(0), n1 = T(0);
+        if (AHEAD && s < G.vn) centre(jv + 1, n0, n1);
+        const T vsq = tV[jv - 1];
+        if (act) {
             T c0;
-            const T F = march_F<T, D>(G, t, jv, tV, cst, PR.dirichlet, c0, m);
+            const T F = march_F<T, D>(G, t, jv, vsq, tdV, c0, m);
             const int64_t g = march_index<D>(G, t, jv);
+            if (!AHEAD) centre(jv, e0, e1);
             T o;
-            if constexpr (OP == OP_STAGE1) o = sc * (F + cG[g]);
-            else if constexpr (OP == OP_STAGE2) o = sc * (F + cG[g]) + (T)A.q * X2[g];
-            else o = T(2) * W[g] - c0 + sc * F;
+            if constexpr (OP == OP_STAGE1) o = sc * (F + e0);
+            else if constexpr (OP == OP_STAGE2) o = sc * (F + e0) + qv * e1;
+            else o = T(2) * e0 - c0 + sc * F;
             W[g] = o;
         }
-        if (more) march_stash<T, D>(G, tid, pn, t, m);   // the slot of plane jv - 2: read last step
+        if (AHEAD) {
+            e0 = n0;
+            e1 = n1;
+        }
+        if (!DEEP && jv + 2 <= last) march_stash<T, D>(G, tid, jv + 2, t, m);
         __syncthreads();
     }
 }
@@ -1624,12 +1667,13 @@ static hipError_t march_td(const DevPlan& P, int op, const StencilArgs& a, hipSt
     if constexpr (D > 4) {
         return hipErrorInvalidValue;
     } else {
-        dim3 g((unsigned)P.n_march), b(MARCH_THREADS);
+        dim3 g((unsigned)(P.xcd ? P.n_march_x : P.n_march)), b(MARCH_THREADS);
         const size_t shm = (size_t)P.march_lds;
+        constexpr int S1 = OP_STAGE1, S2 = OP_STAGE2, RF = OP_REFINE;
         switch (op) {
-        case OP_STAGE1: hipLaunchKernelGGL((k_march<T, D, OP_STAGE1>), g, b, shm, s, P, a); break;
-        case OP_STAGE2: hipLaunchKernelGGL((k_march<T, D, OP_STAGE2>), g, b, shm, s, P, a); break;
-        case OP_REFINE: hipLaunchKernelGGL((k_march<T, D, OP_REFINE>), g, b, shm, s, P, a); break;
+        case S1: hipLaunchKernelGGL((k_march<T, D, S1, march_deep<T, S1>()>), g, b, shm, s, P, a); break;
+        case S2: hipLaunchKernelGGL((k_march<T, D, S2, march_deep<T, S2>()>), g, b, shm, s, P, a); break;
+        case RF: hipLaunchKernelGGL((k_march<T, D, RF, march_deep<T, RF>()>), g, b, shm, s, P, a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "amfrw_march.h"
@@ -118,12 +119,23 @@ struct CheckedMem {
 };
 
 template <int D, int OP>
-int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, int64_t blk_first,
-        int64_t blk_stride, int64_t* n_blocks_out, int64_t* lds_reads_out, int32_t* writes, Err& err)
+int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool deep, bool xorder,
+        int64_t blk_first, int64_t blk_stride, int64_t* n_blocks_out, int64_t* lds_reads_out, int32_t* writes,
+        Err& err)
 {
     std::vector<MarchBlk> blocks;
     march_blocks(D, n_units, lv, MAXD, elem, blocks);
     *n_blocks_out = (int64_t)blocks.size();
+    if (xorder) {                                    // the table the kernel reads when xcd != 0
+        std::vector<MarchBlk> ordered;
+        march_order_xcd(blocks, 8, ordered);
+        if (ordered.size() % 8 != 0) {
+            err("XCD-ordered table is not a whole number of rounds");
+            return 1;
+        }
+        blocks.swap(ordered);
+    }
+    const bool ahead = OP != OP_STAGE2;              // stage values loaded one plane ahead
     std::vector<double> X0((size_t)total, 0.5), X1((size_t)total, 0.25), cG((size_t)total, 0.125),
         X2((size_t)total, 1.0), W((size_t)total, 0.0);
     CheckedMem m;
@@ -133,6 +145,7 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
     int64_t reads = 0;
     for (int64_t bi = blk_first; bi < (int64_t)blocks.size() && !err.set; bi += blk_stride) {
         const MarchBlk& B = blocks[(size_t)bi];
+        if (B.vn == 0) continue;                     // padding: the kernel returns at once
         const int u = B.unit;
         if (u < 0 || u >= n_units) {
             err("block names a unit out of range");
@@ -163,55 +176,83 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
         m.tb = &tb;
         MarchGeo<D> G;
         march_geo<D>(ul, off[u], B, G);
-        if (G.LP > MARCH_MAX_PLANE) {
-            err("plane slot larger than MARCH_MAX_PLANE");
-            break;
+        {
+            const int lt[3] = {B.lt[0], B.lt[1], B.lt[2]};
+            if (G.SLOT > MARCH_MAX_PLANE || G.SLOT != march_slot_elems(D, lt, B.h0)) {
+                err("plane slot larger than MARCH_MAX_PLANE or sized differently from the host");
+                break;
+            }
         }
         if (G.nact > MARCH_THREADS) {
             err("tile has more nodes than threads");
             break;
         }
-        m.reset_lds(MARCH_SLOTS * G.LP);
+        m.reset_lds(MARCH_SLOTS * G.SLOT);      // the kernel's dynamic LDS is sized for the plan's largest slot
         const double* tab = tb.data.data();
         const double* cst = tab + cst0;
         for (int t = 0; t < MARCH_THREADS; ++t) {
             m.tid = t;
             march_thread<double, D>(G, t, thr[(size_t)t]);
             march_coefs<double, D>(G, utab, tab, cst, thr[(size_t)t], m);
+            march_face<double, D>(0, thr[(size_t)t]);
+            march_pads<double, D>(G, t, m);
         }
         const int MV = G.M[D - 1];
         const int last = std::min(MV, G.v0 + G.vn + 1);
-        for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p)
-            for (int t = 0; t < MARCH_THREADS; ++t) {
-                m.tid = t;
-                march_fetch<double, D, OP>(G, t, p, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
+        // the kernel's order: planes v0 .. v0 + 2 fetched and stashed, then (deep pipeline) plane
+        // v0 + 3 fetched, the first node's stage values loaded (all but stage 2), barrier; per step
+        // (deep) stash plane jv + 2 and fetch jv + 3, or (one plane) fetch jv + 2; load the next
+        // node's stage values; compute and store plane jv; (one plane) stash plane jv + 2; barrier
+        auto centre = [&](int t, int jv) {
+            const MarchThr<double, D>& th = thr[(size_t)t];
+            const int64_t g = th.active ? march_index<D>(G, th, jv) : G.off;
+            if (OP == OP_REFINE) return std::make_pair(m.ld(W.data(), g), 0.0);
+            return std::make_pair(m.ld(cG.data(), g), OP == OP_STAGE2 ? m.ld(X2.data(), g) : 0.0);
+        };
+        std::vector<std::pair<double, double>> cur((size_t)MARCH_THREADS), nxt((size_t)MARCH_THREADS);
+        for (int t = 0; t < MARCH_THREADS; ++t) {
+            m.tid = t;
+            for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
+                march_fetch<double, D, OP>(G, p, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
                 march_stash<double, D>(G, t, p, thr[(size_t)t], m);
             }
+            if (deep && G.v0 + 3 <= last)
+                march_fetch<double, D, OP>(G, G.v0 + 3, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
+            cur[(size_t)t] = ahead ? centre(t, G.v0 + 1) : std::make_pair(0.0, 0.0);
+        }
         ++m.epoch;                                           // __syncthreads
         const double* tV = tab + utab[D - 1];
         for (int s = 1; s <= G.vn && !err.set; ++s) {
             const int jv = G.v0 + s;
-            const int pn = jv + 2;
-            const bool more = pn <= last;
             for (int t = 0; t < MARCH_THREADS; ++t) {
                 m.tid = t;
                 MarchThr<double, D>& th = thr[(size_t)t];
-                if (more) march_fetch<double, D, OP>(G, t, pn, X0.data(), X1.data(), 0.5, th, m);
+                if (deep) {
+                    if (jv + 2 <= last) march_stash<double, D>(G, t, jv + 2, th, m);
+                    if (jv + 3 <= last) march_fetch<double, D, OP>(G, jv + 3, X0.data(), X1.data(), 0.5, th, m);
+                } else if (jv + 2 <= last) {
+                    march_fetch<double, D, OP>(G, jv + 2, X0.data(), X1.data(), 0.5, th, m);
+                }
+                nxt[(size_t)t] = ahead && s < G.vn ? centre(t, jv + 1) : std::make_pair(0.0, 0.0);
+                const double vsq = m.tab(tV, jv - 1);
                 if (th.active) {
                     double c0;
-                    const double F = march_F<double, D>(G, th, jv, tV, cst, 0, c0, m);
+                    const double F = march_F<double, D>(G, th, jv, vsq, m.tab(tV, MV), c0, m);
                     const int64_t g = march_index<D>(G, th, jv);
+                    if (!ahead) cur[(size_t)t] = centre(t, jv);
+                    const double e0 = cur[(size_t)t].first, e1 = cur[(size_t)t].second;
                     double o;
-                    if (OP == OP_STAGE1) o = 0.1 * (F + m.ld(cG.data(), g));
-                    else if (OP == OP_STAGE2) o = 0.1 * (F + m.ld(cG.data(), g)) + 0.3 * m.ld(X2.data(), g);
-                    else o = 2.0 * m.ld(W.data(), g) - c0 + 0.1 * F;
+                    if (OP == OP_STAGE1) o = 0.1 * (F + e0);
+                    else if (OP == OP_STAGE2) o = 0.1 * (F + e0) + 0.3 * e1;
+                    else o = 2.0 * e0 - c0 + 0.1 * F;
                     if (g < m.lo || g >= m.hi) err("global write outside the unit");
                     if (g >= 0 && g < total) {
                         W[(size_t)g] = o;
                         writes[g] += 1;
                     }
                 }
-                if (more) march_stash<double, D>(G, t, pn, th, m);
+                if (ahead) cur[(size_t)t] = nxt[(size_t)t];
+                if (!deep && jv + 2 <= last) march_stash<double, D>(G, t, jv + 2, th, m);
             }
             ++m.epoch;                                       // __syncthreads
         }
@@ -222,30 +263,36 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
 }
 
 template <int D>
-int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, int64_t first,
-           int64_t stride, int64_t* nb, int64_t* reads, int32_t* writes, Err& err)
+int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool deep, bool xorder,
+           int64_t first, int64_t stride, int64_t* nb, int64_t* reads, int32_t* writes, Err& err)
 {
-    if (op == OP_STAGE1) return run<D, OP_STAGE1>(n_units, lv, off, total, elem, first, stride, nb, reads, writes, err);
-    if (op == OP_STAGE2) return run<D, OP_STAGE2>(n_units, lv, off, total, elem, first, stride, nb, reads, writes, err);
-    return run<D, OP_REFINE>(n_units, lv, off, total, elem, first, stride, nb, reads, writes, err);
+    if (op == OP_STAGE1)
+        return run<D, OP_STAGE1>(n_units, lv, off, total, elem, deep, xorder, first, stride, nb, reads, writes, err);
+    if (op == OP_STAGE2)
+        return run<D, OP_STAGE2>(n_units, lv, off, total, elem, deep, xorder, first, stride, nb, reads, writes, err);
+    return run<D, OP_REFINE>(n_units, lv, off, total, elem, deep, xorder, first, stride, nb, reads, writes, err);
 }
 
 }  // namespace
 
 extern "C" {
 
-// Walk blocks first, first + stride, ... of the plan's marching operator (every block for stride 1).
-// lv: [n_units][MAXD] levels; off: unit offsets; writes: [total] counters (incremented).  Returns 0
-// when every check passed, else 1 with the first failure in err.
-int march_check(int d, int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem,
-                int64_t first, int64_t stride, int64_t* n_blocks, int64_t* lds_reads, int32_t* writes, char* err,
-                int errlen)
+// Walk entries first, first + stride, ... of the plan's marching-operator block table (every entry
+// for stride 1): the unit-by-unit table, or with xorder the XCD-grouped one; deep selects the
+// two-plane pipeline.  lv: [n_units][MAXD] levels; off: unit offsets; writes: [total] counters
+// (incremented).  Returns 0 when every check passed, else 1 with the first failure in err.
+int march_check(int d, int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, int deep,
+                int xorder, int64_t first, int64_t stride, int64_t* n_blocks, int64_t* lds_reads, int32_t* writes,
+                char* err, int errlen)
 {
     Err e;
     int rc = 2;
-    if (d == 2) rc = run_op<2>(op, n_units, lv, off, total, elem, first, stride, n_blocks, lds_reads, writes, e);
-    else if (d == 3) rc = run_op<3>(op, n_units, lv, off, total, elem, first, stride, n_blocks, lds_reads, writes, e);
-    else if (d == 4) rc = run_op<4>(op, n_units, lv, off, total, elem, first, stride, n_blocks, lds_reads, writes, e);
+    const bool dp = deep != 0, xo = xorder != 0;
+    if (d == 2) rc = run_op<2>(op, n_units, lv, off, total, elem, dp, xo, first, stride, n_blocks, lds_reads, writes, e);
+    else if (d == 3)
+        rc = run_op<3>(op, n_units, lv, off, total, elem, dp, xo, first, stride, n_blocks, lds_reads, writes, e);
+    else if (d == 4)
+        rc = run_op<4>(op, n_units, lv, off, total, elem, dp, xo, first, stride, n_blocks, lds_reads, writes, e);
     else e("d must lie in [2, 4]");
     std::snprintf(err, (size_t)errlen, "%s", e.msg.c_str());
     return e.set ? 1 : rc;

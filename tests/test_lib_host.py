@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(L.EXPORTED)
-    assert lib.amf_abi_version() == 2
+    assert lib.amf_abi_version() == 2 == L.ABI_VERSION
 
 
 def _create(probs, grid, steps=10, prec=L.FP64, rich=0, scheme=None):
