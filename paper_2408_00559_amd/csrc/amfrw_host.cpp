@@ -718,9 +718,14 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             if ((int64_t)P->march_blk.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
             for (const MarchBlk& B : P->march_blk) {
                 const int lt[3] = {B.lt[0], B.lt[1], B.lt[2]};
-                const int slot = march_slot_elems(d, lt, B.h0);
+                const int slot = march_slot_elems(d, lt);
                 if (slot > MARCH_MAX_PLANE) throw std::logic_error("marching tile larger than its LDS slot");
                 P->march_lp = std::max(P->march_lp, slot);
+                // buffer accesses address one V plane of a unit with 32-bit byte offsets
+                const UnitDev& U = P->units[B.unit];
+                int64_t plane = (int64_t)P->elem;
+                for (int i = 0; i < d - 1; ++i) plane <<= U.lv[i];
+                if (plane >= (int64_t)MARCH_NONE) throw std::logic_error("V plane of a unit too large for the marching operator");
             }
             march_order_xcd(P->march_blk, NXCD, P->march_blk_x);
             if ((int64_t)P->march_blk_x.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
@@ -886,7 +891,7 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
     D.march_blk_x = P->march_blk_x.empty() ? nullptr : (const MarchBlk*)(P->ws + P->off_march_x);
     D.n_march = (int64_t)P->march_blk.size();
     D.n_march_x = (int64_t)P->march_blk_x.size();
-    D.march_lds = MARCH_SLOTS * P->march_lp * (int)P->elem;
+    D.march_lds = (MARCH_SLOTS * P->march_lp + MARCH_SEG) * (int)P->elem;   // slot ring + V^2 of the planes
     P->bound = true;
     return AMF_OK;
 }

@@ -535,36 +535,45 @@ __global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilAr
 
 // ------------------------------------------------------------------------------------------------
 // The time-loop operator in its plane-tiled form (amfrw_march.h): one block per (unit, tile of the
-// plane axes, range of V planes); the neighbour values come from a ring of LDS plane slots.
+// plane axes, range of V planes); the neighbour values come from a ring of LDS plane slots.  Global
+// traffic goes through buffer loads and stores on one V plane of the unit at a time: a fetch whose
+// offset lies beyond the plane (the zero halo elements, every element of plane 0) returns 0.
 template <typename T>
 struct GpuMem {
+    using bits = typename std::conditional<sizeof(T) == 8, unsigned int __attribute__((ext_vector_type(2))),
+                                           unsigned int>::type;
+    struct Plane {
+        __amdgpu_buffer_rsrc_t r;
+    };
     T* lds;
-    __device__ __forceinline__ T ld(const T* p, int64_t i) const { return p[i]; }
+    __device__ __forceinline__ Plane plane(const T* p, int64_t base, int64_t n) const
+    {
+        return {__builtin_amdgcn_make_buffer_rsrc((void*)(p + base), (short)0, (int)(n * (int64_t)sizeof(T)),
+                                                  0x00020000)};
+    }
+    __device__ __forceinline__ T pld(const Plane& h, uint32_t b) const
+    {
+        if constexpr (sizeof(T) == 8) return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(h.r, b, 0, 0));
+        else return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(h.r, b, 0, 0));
+    }
+    __device__ __forceinline__ void pst(const Plane& h, uint32_t b, T v) const
+    {
+        if constexpr (sizeof(T) == 8) __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(bits, v), h.r, b, 0, 0);
+        else __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(bits, v), h.r, b, 0, 0);
+    }
     __device__ __forceinline__ T tab(const T* p, int i) const { return p[i]; }
     __device__ __forceinline__ T sr(int i) const { return lds[i]; }
     __device__ __forceinline__ void sw(int i, T v) const { lds[i] = v; }
 };
 
-// The plane pipeline: DEEP keeps two planes in flight (plane j_V + 3 is loaded while plane j_V is
-// computed, plane j_V + 2 written to its slot at the top of the step), else one (plane j_V + 2 is
-// loaded at the top of the step and written to its slot after the compute).  Stage 1 and the
-// refinement also load the next node's stage values one plane ahead; stage 2, which needs two
-// values per node, loads them where they are used.
-template <typename T, int OP>
-constexpr bool march_deep()
+// One block.  Per step: plane j_V + 2 (loaded during the previous step) into its slot, plane j_V + 3
+// and the next node's stage values loaded, plane j_V computed and stored.  Loads are issued in the
+// order they are waited for, so no wait covers a load issued later in the same step.
+template <typename T, int D, int OP, class Sh>
+__device__ __forceinline__ void march_block(const DevPlan& P, const StencilArgs& A, const MarchBlk& B, T* smem)
 {
-    return false;
-}
-
-template <typename T, int D, int OP, bool DEEP>
-__global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs A)
-{
-    static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
-    constexpr bool AHEAD = OP != OP_STAGE2;
-    extern __shared__ __align__(16) unsigned char march_smem[];
-    GpuMem<T> m{(T*)march_smem};
-    const MarchBlk B = (P.xcd ? P.march_blk_x : P.march_blk)[blockIdx.x];
-    if (B.vn == 0) return;                                  // padding of the XCD-ordered table
+    constexpr int NPF = Sh::NPF;
+    GpuMem<T> m{smem};
     const UnitDev& U = P.units[B.unit];
     MarchGeo<D> G;
     march_geo<D>(U.lv, U.off, B, G);
@@ -572,11 +581,10 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs 
     const T* tab = (const T*)P.tab;
     const T* cst = tab + PR.cst;
     const int tid = threadIdx.x;
-    MarchThr<T, D> t;
-    march_thread<T, D>(G, tid, t);
+    MarchThr<T, D, NPF> t;
+    march_thread<T, D, Sh>(G, tid, t);
     march_coefs<T, D>(G, U.tab, tab, cst, t, m);
     march_face<T, D>(PR.dirichlet, t);
-    march_pads<T, D>(G, tid, m);
     const T* X0 = (const T*)A.X0;
     const T* X1 = (const T*)A.X1;
     const T av = (T)A.a;
@@ -586,60 +594,62 @@ __global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs 
     const int MV = G.M[D - 1];
     const T tdV = tV[MV];
     const int last = min(MV, G.v0 + G.vn + 1);            // last plane the block reads
-    const T* cG = (const T*)A.cG;
+    const T* cE = OP == OP_REFINE ? (const T*)A.W : (const T*)A.cG;
     const T* X2 = A.X2 ? (const T*)A.X2 : X1;
     T* W = (T*)A.W;
     const bool act = t.active;
     // the values the stage combination needs at this thread's node of plane jv
-    auto centre = [&](int jv, T& e0, T& e1) {
-        const int64_t g = act ? march_index<D>(G, t, jv) : G.off;
-        if constexpr (OP == OP_REFINE) {
-            e0 = W[g];                                          // K^(0)
-            e1 = T(0);
-        } else {
-            e0 = cG[g];
-            e1 = OP == OP_STAGE2 ? X2[g] : T(0);
-        }
+    auto centre = [&](int jv, T& e0, T& e1, bool live) {
+        const int64_t b = march_plane_base<D>(G, jv), n = live ? march_plane_len<D>(G, jv) : 0;
+        e0 = m.pld(m.plane(cE, b, n), t.gob);                 // K^(0) for the refinement
+        e1 = OP == OP_STAGE2 ? m.pld(m.plane(X2, b, n), t.gob) : T(0);
     };
-    // planes v0 .. v0 + 2 into their slots (plane 0 is the lower face: zeros)
+    march_vsq<T, D, Sh>(G, tid, tV, m);
+    // planes v0 .. v0 + 2 into their slots (plane 0 is the lower face: zeros), plane v0 + 3 in flight
     for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
         march_fetch<T, D, OP>(G, p, X0, X1, av, t, m);
-        march_stash<T, D>(G, tid, p, t, m);
+        march_stash<T, D, Sh>(G, tid, p, t, m);
     }
-    if (DEEP && G.v0 + 3 <= last) march_fetch<T, D, OP>(G, G.v0 + 3, X0, X1, av, t, m);
-    T e0 = T(0), e1 = T(0);
-    if (AHEAD) centre(G.v0 + 1, e0, e1);
+    if (G.v0 + 3 <= last) march_fetch<T, D, OP>(G, G.v0 + 3, X0, X1, av, t, m);
+    T ea0, ea1, eb0 = T(0), eb1 = T(0);
+    centre(G.v0 + 1, ea0, ea1, true);
     __syncthreads();
-    for (int s = 1; s <= G.vn; ++s) {
+    // step s computes plane v0 + s from the stage values in (c0_, c1_) and loads those of the next
+    // plane into (n0_, n1_); the two register pairs alternate, so no value is copied between steps
+    // (a copy would wait for the load just issued).  Every step issues the same loads (empty ranges
+    // past the block's planes), so each wait covers exactly the loads of the step before.
+    auto step = [&](int s, T c0_, T c1_, T& n0_, T& n1_) {
         const int jv = G.v0 + s;
-        // the next plane goes into the slot of plane jv - 2, which the previous step read
-        if (DEEP) {
-            if (jv + 2 <= last) march_stash<T, D>(G, tid, jv + 2, t, m);
-            if (jv + 3 <= last) march_fetch<T, D, OP>(G, jv + 3, X0, X1, av, t, m);
-        } else if (jv + 2 <= last) {
-            march_fetch<T, D, OP>(G, jv + 2, X0, X1, av, t, m);
-        }
-        T n0 = T(0), n1 = T(0);
-        if (AHEAD && s < G.vn) centre(jv + 1, n0, n1);
-        const T vsq = tV[jv - 1];
+        // plane jv + 2 goes into the slot of plane jv - 2, which the previous step read
+        if (jv + 2 <= last) march_stash<T, D, Sh>(G, tid, jv + 2, t, m);
+        march_fetch<T, D, OP>(G, jv + 3, X0, X1, av, t, m, jv + 3 <= last);
+        centre(jv + 1, n0_, n1_, s < G.vn);
+        const T vsq = march_vsq_of<T, D, Sh>(G, s, m);
         if (act) {
             T c0;
-            const T F = march_F<T, D>(G, t, jv, vsq, tdV, c0, m);
-            const int64_t g = march_index<D>(G, t, jv);
-            if (!AHEAD) centre(jv, e0, e1);
+            const T F = march_F<T, D, Sh>(G, t, jv, vsq, tdV, c0, m);
             T o;
-            if constexpr (OP == OP_STAGE1) o = sc * (F + e0);
-            else if constexpr (OP == OP_STAGE2) o = sc * (F + e0) + qv * e1;
-            else o = T(2) * e0 - c0 + sc * F;
-            W[g] = o;
+            if constexpr (OP == OP_STAGE1) o = sc * (F + c0_);
+            else if constexpr (OP == OP_STAGE2) o = sc * (F + c0_) + qv * c1_;
+            else o = T(2) * c0_ - c0 + sc * F;
+            m.pst(m.plane(W, march_plane_base<D>(G, jv), march_plane_len<D>(G, jv)), t.gob, o);
         }
-        if (AHEAD) {
-            e0 = n0;
-            e1 = n1;
-        }
-        if (!DEEP && jv + 2 <= last) march_stash<T, D>(G, tid, jv + 2, t, m);
         __syncthreads();
+    };
+    for (int s = 1; s <= G.vn; s += 2) {
+        step(s, ea0, ea1, eb0, eb1);
+        if (s + 1 <= G.vn) step(s + 1, eb0, eb1, ea0, ea1);
     }
+}
+
+template <typename T, int D, int OP>
+__global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs A)
+{
+    static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
+    extern __shared__ __align__(16) unsigned char march_smem[];
+    const MarchBlk B = (P.xcd ? P.march_blk_x : P.march_blk)[blockIdx.x];
+    if (B.vn == 0) return;                                  // padding of the XCD-ordered table
+    march_dispatch<D>(B.shape, [&](auto sh) { march_block<T, D, OP, decltype(sh)>(P, A, B, (T*)march_smem); });
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1669,11 +1679,10 @@ static hipError_t march_td(const DevPlan& P, int op, const StencilArgs& a, hipSt
     } else {
         dim3 g((unsigned)(P.xcd ? P.n_march_x : P.n_march)), b(MARCH_THREADS);
         const size_t shm = (size_t)P.march_lds;
-        constexpr int S1 = OP_STAGE1, S2 = OP_STAGE2, RF = OP_REFINE;
         switch (op) {
-        case S1: hipLaunchKernelGGL((k_march<T, D, S1, march_deep<T, S1>()>), g, b, shm, s, P, a); break;
-        case S2: hipLaunchKernelGGL((k_march<T, D, S2, march_deep<T, S2>()>), g, b, shm, s, P, a); break;
-        case RF: hipLaunchKernelGGL((k_march<T, D, RF, march_deep<T, RF>()>), g, b, shm, s, P, a); break;
+        case OP_STAGE1: hipLaunchKernelGGL((k_march<T, D, OP_STAGE1>), g, b, shm, s, P, a); break;
+        case OP_STAGE2: hipLaunchKernelGGL((k_march<T, D, OP_STAGE2>), g, b, shm, s, P, a); break;
+        case OP_REFINE: hipLaunchKernelGGL((k_march<T, D, OP_REFINE>), g, b, shm, s, P, a); break;
         default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

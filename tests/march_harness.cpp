@@ -69,6 +69,29 @@ struct CheckedMem {
         if (i < 0 || i >= total) return 0.0;
         return p[i];
     }
+    // one V plane of the unit inside a grid vector (the kernel's buffer resource): a fetch beyond it
+    // reads 0 on the GPU, which only the zero elements (MARCH_NONE) and plane 0 (length 0) may rely on
+    struct Plane {
+        const double* p;
+        int64_t base, n;
+    };
+    Plane plane(const double* p, int64_t base, int64_t n)
+    {
+        if (n < 0 || (n > 0 && (base < lo || base + n > hi)))
+            (*err)("plane range outside the unit: [" + std::to_string(base) + ", +" + std::to_string(n) + ")");
+        return {p, base, n};
+    }
+    double pld(const Plane& h, uint32_t b)
+    {
+        if (b == MARCH_NONE || h.n == 0) return 0.0;
+        if (b % sizeof(double) != 0) (*err)("misaligned byte offset " + std::to_string(b));
+        const int64_t i = (int64_t)(b / sizeof(double));
+        if (i >= h.n) {
+            (*err)("fetch beyond its plane: element " + std::to_string(i) + " of " + std::to_string(h.n));
+            return 0.0;
+        }
+        return ld(h.p, h.base + i);
+    }
     double tab(const double* p, int i)
     {
         // find the table block p points into
@@ -118,10 +141,131 @@ struct CheckedMem {
     }
 };
 
+// One block in the kernel's order: V^2 factors into LDS, planes v0 .. v0 + 2 fetched and stashed,
+// plane v0 + 3 fetched, the first node's stage values loaded, barrier; per step stash plane jv + 2,
+// fetch plane jv + 3 (an empty range past the block's last plane), load the next node's stage values
+// (an empty range on the last step), compute and store plane jv, barrier.
+template <int D, int OP, class Sh>
+void walk_block(const MarchBlk& B, const int8_t* ul, int64_t uoff, int64_t total, CheckedMem& m, std::vector<double>& X0,
+                std::vector<double>& X1, std::vector<double>& cG, std::vector<double>& X2, std::vector<double>& W,
+                int32_t* writes, Err& err)
+{
+    constexpr int NPF = Sh::NPF;
+    // the unit's tables: blocks per axis, then the constant block
+    Tables tb;
+    int32_t at = 0;
+    int32_t utab[MAXD] = {};
+    for (int i = 0; i < D; ++i) {
+        const int M = 1 << ul[i];
+        const int sz = i < D - 1 ? 3 * M : M + 2;
+        utab[i] = at;
+        tb.start.push_back(at);
+        tb.size.push_back(sz);
+        at += sz;
+    }
+    const int32_t cst0 = at;
+    tb.start.push_back(at);
+    tb.size.push_back(CST_SIZE);
+    at += CST_SIZE;
+    tb.data.assign((size_t)at, 0.01);
+    m.tb = &tb;
+    MarchGeo<D> G;
+    march_geo<D>(ul, uoff, B, G);
+    {
+        const int lt[3] = {B.lt[0], B.lt[1], B.lt[2]};
+        if (G.LP > MARCH_MAX_PLANE || G.LP != march_slot_elems(D, lt)) {
+            err("plane slot larger than MARCH_MAX_PLANE or sized differently from the host");
+            return;
+        }
+        if (B.shape != march_shape_id(D, lt)) {
+            err("block shape index differs from its tile");
+            return;
+        }
+    }
+    if (G.nact > MARCH_THREADS) {
+        err("tile has more nodes than threads");
+        return;
+    }
+    if (Sh::FULL && (G.nact != MARCH_THREADS || Sh::t0(G) != G.T[0] || Sh::t1(G) != G.T[1] || Sh::s1(G) != G.S1 ||
+                     Sh::s2(G) != G.S2 || Sh::lp(G) != G.LP)) {
+        err("compiled stride set differs from the block's tile");
+        return;
+    }
+    if (!Sh::FULL && NPF * MARCH_THREADS < G.LP) {
+        err("prefetch registers do not cover the slot");
+        return;
+    }
+    m.reset_lds(MARCH_SLOTS * G.LP + MARCH_SEG);   // slot ring + V^2 words (sized for the plan's largest slot)
+    const double* tab = tb.data.data();
+    const double* cst = tab + cst0;
+    std::vector<MarchThr<double, D, NPF>> thr(MARCH_THREADS);
+    for (int t = 0; t < MARCH_THREADS; ++t) {
+        m.tid = t;
+        march_thread<double, D, Sh>(G, t, thr[(size_t)t]);
+        march_coefs<double, D>(G, utab, tab, cst, thr[(size_t)t], m);
+        march_face<double, D>(0, thr[(size_t)t]);
+    }
+    const int MV = G.M[D - 1];
+    const int last = std::min(MV, G.v0 + G.vn + 1);
+    const double* cE = OP == OP_REFINE ? W.data() : cG.data();
+    auto centre = [&](int t, int jv, bool live) {
+        const MarchThr<double, D, NPF>& th = thr[(size_t)t];
+        const int64_t b = march_plane_base<D>(G, jv), n = live ? march_plane_len<D>(G, jv) : 0;
+        const double e0 = m.pld(m.plane(cE, b, n), th.gob);
+        const double e1 = OP == OP_STAGE2 ? m.pld(m.plane(X2.data(), b, n), th.gob) : 0.0;
+        return std::make_pair(e0, e1);
+    };
+    const double* tV = tab + utab[D - 1];
+    std::vector<std::pair<double, double>> cur((size_t)MARCH_THREADS), nxt((size_t)MARCH_THREADS);
+    for (int t = 0; t < MARCH_THREADS; ++t) {
+        m.tid = t;
+        march_vsq<double, D, Sh>(G, t, tV, m);
+        for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
+            march_fetch<double, D, OP>(G, p, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
+            march_stash<double, D, Sh>(G, t, p, thr[(size_t)t], m);
+        }
+        if (G.v0 + 3 <= last) march_fetch<double, D, OP>(G, G.v0 + 3, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
+        cur[(size_t)t] = centre(t, G.v0 + 1, true);
+    }
+    ++m.epoch;                                               // __syncthreads
+    for (int s = 1; s <= G.vn && !err.set; ++s) {
+        const int jv = G.v0 + s;
+        for (int t = 0; t < MARCH_THREADS; ++t) {
+            m.tid = t;
+            MarchThr<double, D, NPF>& th = thr[(size_t)t];
+            if (jv + 2 <= last) march_stash<double, D, Sh>(G, t, jv + 2, th, m);
+            march_fetch<double, D, OP>(G, jv + 3, X0.data(), X1.data(), 0.5, th, m, jv + 3 <= last);
+            nxt[(size_t)t] = centre(t, jv + 1, s < G.vn);
+            const double vsq = march_vsq_of<double, D, Sh>(G, s, m);
+            if (th.active) {
+                double c0;
+                const double F = march_F<double, D, Sh>(G, th, jv, vsq, m.tab(tV, MV), c0, m);
+                const double e0 = cur[(size_t)t].first, e1 = cur[(size_t)t].second;
+                double o;
+                if (OP == OP_STAGE1) o = 0.1 * (F + e0);
+                else if (OP == OP_STAGE2) o = 0.1 * (F + e0) + 0.3 * e1;
+                else o = 2.0 * e0 - c0 + 0.1 * F;
+                const CheckedMem::Plane hw = m.plane(W.data(), march_plane_base<D>(G, jv), march_plane_len<D>(G, jv));
+                if (hw.n == 0 || th.gob % sizeof(double) != 0 || (int64_t)(th.gob / sizeof(double)) >= hw.n) {
+                    err("store outside its plane");
+                } else {
+                    const int64_t g = hw.base + (int64_t)(th.gob / sizeof(double));
+                    if (g < m.lo || g >= m.hi) err("global write outside the unit");
+                    if (g >= 0 && g < total) {
+                        W[(size_t)g] = o;
+                        writes[g] += 1;
+                    }
+                }
+            }
+            cur[(size_t)t] = nxt[(size_t)t];
+        }
+        ++m.epoch;                                           // __syncthreads
+    }
+}
+
 template <int D, int OP>
-int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool deep, bool xorder,
-        int64_t blk_first, int64_t blk_stride, int64_t* n_blocks_out, int64_t* lds_reads_out, int32_t* writes,
-        Err& err)
+int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool xorder, int64_t blk_first,
+        int64_t blk_stride, int64_t* n_blocks_out, int64_t* lds_reads_out, int32_t* writes, Err& err)
 {
     std::vector<MarchBlk> blocks;
     march_blocks(D, n_units, lv, MAXD, elem, blocks);
@@ -135,14 +279,11 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
         }
         blocks.swap(ordered);
     }
-    const bool ahead = OP != OP_STAGE2;              // stage values loaded one plane ahead
     std::vector<double> X0((size_t)total, 0.5), X1((size_t)total, 0.25), cG((size_t)total, 0.125),
         X2((size_t)total, 1.0), W((size_t)total, 0.0);
     CheckedMem m;
     m.err = &err;
     m.total = total;
-    std::vector<MarchThr<double, D>> thr(MARCH_THREADS);
-    int64_t reads = 0;
     for (int64_t bi = blk_first; bi < (int64_t)blocks.size() && !err.set; bi += blk_stride) {
         const MarchBlk& B = blocks[(size_t)bi];
         if (B.vn == 0) continue;                     // padding: the kernel returns at once
@@ -156,121 +297,21 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
         for (int i = 0; i < D; ++i) lsum += ul[i];
         m.lo = off[u];
         m.hi = off[u] + ((int64_t)1 << lsum);
-        // the unit's tables: blocks per axis, then the constant block
-        Tables tb;
-        int32_t at = 0;
-        int32_t utab[MAXD] = {};
-        for (int i = 0; i < D; ++i) {
-            const int M = 1 << ul[i];
-            const int sz = i < D - 1 ? 3 * M : M + 2;
-            utab[i] = at;
-            tb.start.push_back(at);
-            tb.size.push_back(sz);
-            at += sz;
-        }
-        const int32_t cst0 = at;
-        tb.start.push_back(at);
-        tb.size.push_back(CST_SIZE);
-        at += CST_SIZE;
-        tb.data.assign((size_t)at, 0.01);
-        m.tb = &tb;
-        MarchGeo<D> G;
-        march_geo<D>(ul, off[u], B, G);
-        {
-            const int lt[3] = {B.lt[0], B.lt[1], B.lt[2]};
-            if (G.SLOT > MARCH_MAX_PLANE || G.SLOT != march_slot_elems(D, lt, B.h0)) {
-                err("plane slot larger than MARCH_MAX_PLANE or sized differently from the host");
-                break;
-            }
-        }
-        if (G.nact > MARCH_THREADS) {
-            err("tile has more nodes than threads");
-            break;
-        }
-        m.reset_lds(MARCH_SLOTS * G.SLOT);      // the kernel's dynamic LDS is sized for the plan's largest slot
-        const double* tab = tb.data.data();
-        const double* cst = tab + cst0;
-        for (int t = 0; t < MARCH_THREADS; ++t) {
-            m.tid = t;
-            march_thread<double, D>(G, t, thr[(size_t)t]);
-            march_coefs<double, D>(G, utab, tab, cst, thr[(size_t)t], m);
-            march_face<double, D>(0, thr[(size_t)t]);
-            march_pads<double, D>(G, t, m);
-        }
-        const int MV = G.M[D - 1];
-        const int last = std::min(MV, G.v0 + G.vn + 1);
-        // the kernel's order: planes v0 .. v0 + 2 fetched and stashed, then (deep pipeline) plane
-        // v0 + 3 fetched, the first node's stage values loaded (all but stage 2), barrier; per step
-        // (deep) stash plane jv + 2 and fetch jv + 3, or (one plane) fetch jv + 2; load the next
-        // node's stage values; compute and store plane jv; (one plane) stash plane jv + 2; barrier
-        auto centre = [&](int t, int jv) {
-            const MarchThr<double, D>& th = thr[(size_t)t];
-            const int64_t g = th.active ? march_index<D>(G, th, jv) : G.off;
-            if (OP == OP_REFINE) return std::make_pair(m.ld(W.data(), g), 0.0);
-            return std::make_pair(m.ld(cG.data(), g), OP == OP_STAGE2 ? m.ld(X2.data(), g) : 0.0);
-        };
-        std::vector<std::pair<double, double>> cur((size_t)MARCH_THREADS), nxt((size_t)MARCH_THREADS);
-        for (int t = 0; t < MARCH_THREADS; ++t) {
-            m.tid = t;
-            for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
-                march_fetch<double, D, OP>(G, p, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
-                march_stash<double, D>(G, t, p, thr[(size_t)t], m);
-            }
-            if (deep && G.v0 + 3 <= last)
-                march_fetch<double, D, OP>(G, G.v0 + 3, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
-            cur[(size_t)t] = ahead ? centre(t, G.v0 + 1) : std::make_pair(0.0, 0.0);
-        }
-        ++m.epoch;                                           // __syncthreads
-        const double* tV = tab + utab[D - 1];
-        for (int s = 1; s <= G.vn && !err.set; ++s) {
-            const int jv = G.v0 + s;
-            for (int t = 0; t < MARCH_THREADS; ++t) {
-                m.tid = t;
-                MarchThr<double, D>& th = thr[(size_t)t];
-                if (deep) {
-                    if (jv + 2 <= last) march_stash<double, D>(G, t, jv + 2, th, m);
-                    if (jv + 3 <= last) march_fetch<double, D, OP>(G, jv + 3, X0.data(), X1.data(), 0.5, th, m);
-                } else if (jv + 2 <= last) {
-                    march_fetch<double, D, OP>(G, jv + 2, X0.data(), X1.data(), 0.5, th, m);
-                }
-                nxt[(size_t)t] = ahead && s < G.vn ? centre(t, jv + 1) : std::make_pair(0.0, 0.0);
-                const double vsq = m.tab(tV, jv - 1);
-                if (th.active) {
-                    double c0;
-                    const double F = march_F<double, D>(G, th, jv, vsq, m.tab(tV, MV), c0, m);
-                    const int64_t g = march_index<D>(G, th, jv);
-                    if (!ahead) cur[(size_t)t] = centre(t, jv);
-                    const double e0 = cur[(size_t)t].first, e1 = cur[(size_t)t].second;
-                    double o;
-                    if (OP == OP_STAGE1) o = 0.1 * (F + e0);
-                    else if (OP == OP_STAGE2) o = 0.1 * (F + e0) + 0.3 * e1;
-                    else o = 2.0 * e0 - c0 + 0.1 * F;
-                    if (g < m.lo || g >= m.hi) err("global write outside the unit");
-                    if (g >= 0 && g < total) {
-                        W[(size_t)g] = o;
-                        writes[g] += 1;
-                    }
-                }
-                if (ahead) cur[(size_t)t] = nxt[(size_t)t];
-                if (!deep && jv + 2 <= last) march_stash<double, D>(G, t, jv + 2, th, m);
-            }
-            ++m.epoch;                                       // __syncthreads
-        }
+        march_dispatch<D>(B.shape, [&](auto sh) {
+            walk_block<D, OP, decltype(sh)>(B, ul, off[u], total, m, X0, X1, cG, X2, W, writes, err);
+        });
     }
-    reads += m.reads;
-    *lds_reads_out = reads;
+    *lds_reads_out = m.reads;
     return err.set ? 1 : 0;
 }
 
 template <int D>
-int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool deep, bool xorder,
+int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool xorder,
            int64_t first, int64_t stride, int64_t* nb, int64_t* reads, int32_t* writes, Err& err)
 {
-    if (op == OP_STAGE1)
-        return run<D, OP_STAGE1>(n_units, lv, off, total, elem, deep, xorder, first, stride, nb, reads, writes, err);
-    if (op == OP_STAGE2)
-        return run<D, OP_STAGE2>(n_units, lv, off, total, elem, deep, xorder, first, stride, nb, reads, writes, err);
-    return run<D, OP_REFINE>(n_units, lv, off, total, elem, deep, xorder, first, stride, nb, reads, writes, err);
+    if (op == OP_STAGE1) return run<D, OP_STAGE1>(n_units, lv, off, total, elem, xorder, first, stride, nb, reads, writes, err);
+    if (op == OP_STAGE2) return run<D, OP_STAGE2>(n_units, lv, off, total, elem, xorder, first, stride, nb, reads, writes, err);
+    return run<D, OP_REFINE>(n_units, lv, off, total, elem, xorder, first, stride, nb, reads, writes, err);
 }
 
 }  // namespace
@@ -278,21 +319,19 @@ int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t to
 extern "C" {
 
 // Walk entries first, first + stride, ... of the plan's marching-operator block table (every entry
-// for stride 1): the unit-by-unit table, or with xorder the XCD-grouped one; deep selects the
-// two-plane pipeline.  lv: [n_units][MAXD] levels; off: unit offsets; writes: [total] counters
-// (incremented).  Returns 0 when every check passed, else 1 with the first failure in err.
-int march_check(int d, int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, int deep,
-                int xorder, int64_t first, int64_t stride, int64_t* n_blocks, int64_t* lds_reads, int32_t* writes,
-                char* err, int errlen)
+// for stride 1): the unit-by-unit table, or with xorder the XCD-grouped one.  lv: [n_units][MAXD]
+// levels; off: unit offsets; writes: [total] counters (incremented).  Returns 0 when every check
+// passed, else 1 with the first failure in err.
+int march_check(int d, int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, int xorder,
+                int64_t first, int64_t stride, int64_t* n_blocks, int64_t* lds_reads, int32_t* writes, char* err,
+                int errlen)
 {
     Err e;
     int rc = 2;
-    const bool dp = deep != 0, xo = xorder != 0;
-    if (d == 2) rc = run_op<2>(op, n_units, lv, off, total, elem, dp, xo, first, stride, n_blocks, lds_reads, writes, e);
-    else if (d == 3)
-        rc = run_op<3>(op, n_units, lv, off, total, elem, dp, xo, first, stride, n_blocks, lds_reads, writes, e);
-    else if (d == 4)
-        rc = run_op<4>(op, n_units, lv, off, total, elem, dp, xo, first, stride, n_blocks, lds_reads, writes, e);
+    const bool xo = xorder != 0;
+    if (d == 2) rc = run_op<2>(op, n_units, lv, off, total, elem, xo, first, stride, n_blocks, lds_reads, writes, e);
+    else if (d == 3) rc = run_op<3>(op, n_units, lv, off, total, elem, xo, first, stride, n_blocks, lds_reads, writes, e);
+    else if (d == 4) rc = run_op<4>(op, n_units, lv, off, total, elem, xo, first, stride, n_blocks, lds_reads, writes, e);
     else e("d must lie in [2, 4]");
     std::snprintf(err, (size_t)errlen, "%s", e.msg.c_str());
     return e.set ? 1 : rc;
