@@ -281,6 +281,80 @@ def run_fg2d(torch, Plan, reps=200):
     return out
 
 
+def run_paper_tables(torch, Plan):
+    """The paper's own Section 6 runs on this GPU in FP64 (the paper's precision), against the
+    prices and times it prints (tests/golden/paper_tables.json; the paper's times are from its own
+    CPU runs and are context, not a target): Table sg_d4 (standard technique, 8 steps, levels
+    12-17), Table d4:level (psi = 1, 2, levels 9-13, 16 steps) and Table d1:Level (caplet, psi = 1,
+    2, levels 7-14, 256 steps).  Then two comparisons the method motivates at d = 4, psi = 1,
+    16 steps: Neumann against Dirichlet rate faces (eq. (bound1) vs eq. (bound1_0)), and the cost
+    per step of AMFR-W2 against the theta-method with one Gauss-Seidel sweep (W = P, Section 4.2).
+    Each solve is timed on its second call (the first builds and caches the launch graph)."""
+    import numpy as np
+
+    from paper_2408_00559_amd import inputs as I
+    from paper_2408_00559_amd import solver as S
+
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_tables.json")))
+
+    def solve(problem, grid, steps, scheme=None):
+        plan = Plan([problem], grid, steps, precision="fp64", scheme=scheme, device="cuda:0")
+        plan.set_schedule(march=1 if plan.schedule()["march_available"] else 0, xcd_remap=1, fuse_axis0=0)
+        plan.use_graph(True)
+        pr = torch.empty(1, dtype=torch.float64, device="cuda:0")
+        plan.solve()
+        plan.combine(pr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.solve()
+        plan.combine(pr)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        out = (float(pr.item()) * 1e4, sec, plan.inner_points)
+        del plan
+        return out
+
+    def table(name, problem_of, rows, keep=lambda r: True):
+        res = []
+        for r in rows:
+            if not keep(r):
+                continue
+            psi, n, steps, ref, paper_s = r[0], r[1], r[2], r[3], r[4]
+            v, sec, pts = solve(problem_of(), I.combination(n, psi), steps)
+            res.append({"psi": psi, "n": n, "steps": steps, "price_bps": v, "paper_bps": ref,
+                        "rel_diff": abs(v - ref) / abs(ref), "gpu_s": sec, "paper_s": paper_s,
+                        "inner_points": pts})
+        torch.cuda.empty_cache()
+        return {"table": name, "rows": res, "max_rel_diff": max(x["rel_diff"] for x in res)}
+
+    out = {
+        "sg_d4": table("sg_d4", lambda: I.paper_swaption(3), gold["sg_d4"]["rows"], lambda r: r[2] == 8),
+        "d4_level": table("d4:level", lambda: I.paper_swaption(3), gold["d4_level_all"]["rows"]),
+        "d1_level": table("d1:Level", I.paper_caplet, gold["d1_level_all"]["rows"]),
+    }
+    # boundary kinds at d = 4 (no printed Dirichlet values: the two series side by side)
+    bc = []
+    for n in (9, 10, 11, 12):
+        neu = solve(I.paper_swaption(3), I.combination(n, 1), 16)[0]
+        q = I.paper_swaption(3)
+        q.boundary = I.DIRICHLET
+        dir_ = solve(q, I.combination(n, 1), 16)[0]
+        bc.append({"n": n, "neumann_bps": neu, "dirichlet_bps": dir_})
+    out["boundary_d4_psi1"] = bc
+    # cost per step: AMFR-W2 (two stages, AMF W) and Crank-Nicolson with s Gauss-Seidel sweeps
+    # (theta = 1/2, W = P; order 2 for s >= 2)
+    steps = 16
+    w2 = solve(I.paper_swaption(3), I.combination(9, 1), steps)
+    cost = {"steps": steps, "paper_bps_d4_level_n9": gold["d4_level_all"]["rows"][0][3],
+            "amfrw2": {"price_bps": w2[0], "ms_per_step": w2[1] * 1e3 / steps}}
+    for st in (2, 4):
+        gs = solve(I.paper_swaption(3), I.combination(9, 1), steps, scheme=S.scheme_theta_gs(0.5, st))
+        cost["theta_half_gauss_seidel_s%d" % st] = {"price_bps": gs[0], "ms_per_step": gs[1] * 1e3 / steps}
+    out["scheme_cost_d4_psi1_n9"] = cost
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_ct6(torch, Plan):
     """d = 6 (5 rates + V), modified combination n = 8, psi = 1 (2975 component grids): FP32
     stencil and sweeps with FP64 combination, fourth order in time by Richardson extrapolation of
@@ -429,7 +503,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-ct6", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--only", choices=["serving", "ct6", "surrogate", "fg2d"], default=None,
+    ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--only", choices=["serving", "ct6", "surrogate", "fg2d", "paper"], default=None,
                     help="run one secondary section alone and print its JSON (profiling runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/hbm_traffic_ct4.json from two rocprofv3 --pmc runs")
@@ -452,7 +527,8 @@ def main():
     from paper_2408_00559_amd.solver import Plan
 
     if args.only:
-        run = {"serving": run_serving, "ct6": run_ct6, "surrogate": run_surrogate, "fg2d": run_fg2d}[args.only]
+        run = {"serving": run_serving, "ct6": run_ct6, "surrogate": run_surrogate, "fg2d": run_fg2d,
+               "paper": run_paper_tables}[args.only]
         print(json.dumps({args.only: run(torch, Plan)}), flush=True)
         return
     w = I.workload_ct4()
@@ -512,6 +588,8 @@ def main():
         res["ct6_fp32_richardson"] = run_ct6(torch, Plan)
     if not args.no_surrogate:
         res["surrogate"] = run_surrogate(torch, Plan)
+    if not args.no_paper:
+        res["paper_tables"] = run_paper_tables(torch, Plan)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(res), flush=True)

@@ -110,8 +110,8 @@ typedef struct {
 typedef struct {
     uint32_t struct_size;
     int32_t full_grid;                          /* 1: levels[] is used; 0: n and psi are used     */
-    int32_t levels[AMF_MAX_D];                  /* 0 <= level <= 16                               */
-    int32_t n;                                  /* n >= d - 1 (coefficients then sum to 1)       */
+    int32_t levels[AMF_MAX_D];                  /* 0 <= level <= 20                               */
+    int32_t n;                                  /* d - 1 <= n, n + psi <= 20, n + d psi <= 30     */
     int32_t psi;                                /* 0 <= psi <= 8                                  */
 } amf_grid_spec;
 
@@ -154,8 +154,8 @@ amf_status amf_scheme_theta_gs(double theta, int32_t stages, amf_scheme* out);
  * per problem.  richardson = 1 also runs 2*n_steps and combines prices as (8 P_fine - P_coarse)/7
  * (fourth order in time from a third-order scheme such as AMFR-W2).  Errors: AMF_E_INVALID for
  * out-of-range descriptors (d, levels, n < d-1, psi, beta, correlations, boundary, x_eval outside
- * the domain, steps < 1, stages, w_matrix, theta, nu), AMF_E_UNSUPPORTED for an axis-1 level above
- * 10. */
+ * the domain, steps < 1, stages, w_matrix, theta, nu), AMF_E_UNSUPPORTED for the W = P scheme
+ * (w_matrix = AMF_W_LOWER) on a grid with an axis-1 level above 10. */
 amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_grid_spec* grid,
                            const amf_scheme* scheme, amf_precision precision, int32_t n_steps,
                            int32_t richardson, amf_plan** out);
@@ -235,9 +235,10 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
  *                  schedule: one launch per operator / axis over all grids.
  *   fuse_axis0:    streaming schedule only: 1 = the time-loop operator launches also solve the
  *                  axis-1 systems of the first AMF factor (Lemma lema:ls) on the values they
- *                  produce, so no separate axis-1 sweep runs; allowed when stencil_nodes >= 2 and
+ *                  produce, so no separate axis-1 sweep runs; allowed when stencil_nodes >= 2,
  *                  256 * stencil_nodes >= the longest axis-1 line (fuse_max_axis0 reports that
- *                  line length); 0 = separate axis-1 sweep launches.
+ *                  line length) and that line has at most 1024 points; 0 = separate axis-1 sweep
+ *                  launches.
  *   march:         streaming schedule, d <= 4 only (march_available): 1 = the time-loop operators
  *                  run plane-tiled, one block per (grid, tile of the axes 1..d-1, range of V
  *                  planes) walking the V axis with the tile's neighbourhood in an LDS ring of

@@ -5,6 +5,7 @@
 namespace amf {
 
 constexpr int MAXD = 6;            // kernels are instantiated for d = 2..6
+constexpr int MAX_LEVEL = 20;      // per-axis level: at most 2^20 inner points on one axis
 
 // Per-problem constants in the plan precision, at ProbDev::cst inside the table array.
 enum CstIndex : int {

@@ -340,22 +340,25 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         std::vector<int> row(d);
         int s = 0;
         for (int i = 0; i < d; ++i) {
-            if (grid->levels[i] < 0 || grid->levels[i] > 16) return fail(AMF_E_INVALID, "levels must lie in [0, 16]");
+            if (grid->levels[i] < 0 || grid->levels[i] > MAX_LEVEL)
+                return fail(AMF_E_INVALID, "levels must lie in [0, " + std::to_string(MAX_LEVEL) + "]");
             row[i] = grid->levels[i];
             s += row[i];
         }
         if (s > 30) return fail(AMF_E_INVALID, "full grid too large (sum of levels > 30)");
-        if (row[0] > 10) return fail(AMF_E_UNSUPPORTED, "axis-1 level above 10 is not built");
         glv.push_back(row);
         gcf.push_back(1.0);
     } else {
         if (grid->psi < 0 || grid->psi > 8) return fail(AMF_E_INVALID, "psi must lie in [0, 8]");
         if (grid->n < d - 1) return fail(AMF_E_INVALID, "n must be >= d-1 (combination coefficients sum to 1)");
-        if (grid->psi + grid->n > 16 || d * grid->psi + grid->n > 30)
+        if (grid->psi + grid->n > MAX_LEVEL || d * grid->psi + grid->n > 30)
             return fail(AMF_E_INVALID, "combination level too large");
-        if (grid->psi + grid->n > 10) return fail(AMF_E_UNSUPPORTED, "axis-1 level above 10 is not built");
         enumerate_grids(d, grid->n, grid->psi, glv, gcf);
     }
+    if (scheme->w_matrix == AMF_W_LOWER)
+        for (const std::vector<int>& row : glv)
+            if (row[0] > CONTIG_PART_LM)
+                return fail(AMF_E_UNSUPPORTED, "the W = P solve takes axis-1 levels up to " + std::to_string(CONTIG_PART_LM));
 
     amf_plan* P = new (std::nothrow) amf_plan();
     if (!P) return fail(AMF_E_NOMEM, "out of host memory");
@@ -426,7 +429,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             }
             // axis tables for every level in use on that axis
             std::vector<int64_t> blk_of[MAXD];
-            for (int i = 0; i < d; ++i) blk_of[i].assign(17, -1);
+            for (int i = 0; i < d; ++i) blk_of[i].assign(MAX_LEVEL + 1, -1);
             T.unit_tab.assign((size_t)ng * d, 0);
             for (int g = 0; g < ng; ++g)
                 for (int i = 0; i < d; ++i) {
@@ -438,7 +441,8 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                     T.unit_tab[(size_t)g * d + i] = blk_of[i][L];
                 }
             // Thomas factors per (axis, level, V level) in use, both runs (axis 0: the fused solve)
-            std::vector<std::vector<int64_t>> fac_of(d, std::vector<int64_t>(17 * 17, -1));
+            constexpr int NL = MAX_LEVEL + 1;
+            std::vector<std::vector<int64_t>> fac_of(d, std::vector<int64_t>(NL * NL, -1));
             // FP64 weights delta_r = d_ax / h_ax^2 along a line (as the coefficient tables hold them)
             std::vector<double> dl;
             auto delta_of = [&](int ax, int L, int LV, int jv, const std::vector<double>& t,
@@ -454,7 +458,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             for (int g = 0; g < ng; ++g)
                 for (int i = 0; i < d; ++i) {
                     const int L = glv[g][i], LV = glv[g][d - 1];
-                    const int key = (i < d - 1) ? L * 17 + LV : L * 17 + L;
+                    const int key = (i < d - 1) ? L * NL + LV : L * NL + L;
                     if (fac_of[i][key] < 0) {
                         fac_of[i][key] = (int64_t)T.fac[0].size();
                         const int nlines = (i < d - 1) ? (1 << LV) : 1;
@@ -559,7 +563,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         block_table(NODE_BLOCK, P->blk_unit);
         for (int k = 0; k < 4; ++k) block_table((int64_t)NODE_BLOCK << k, P->blk_unit_r[k]);
         // time-loop operator: R consecutive axis-0 nodes per thread, R <= every unit's M_0
-        int min_m0 = 1 << 16, max_m0 = 1;
+        int min_m0 = 1 << MAX_LEVEL, max_m0 = 1;
         for (int u = 0; u < P->n_units; ++u) {
             min_m0 = std::min(min_m0, 1 << P->units[u].lv[0]);
             max_m0 = std::max(max_m0, 1 << P->units[u].lv[0]);
@@ -637,13 +641,16 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                     continue;
                 }
                 int k = k0;
-                // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each
-                // longer strided lines: M/seg_rows threads per line slot in blocks of SEG_BLOCK threads
+                // axis 0 lines longer than 2^CONTIG_REG_LM take M/SEG lanes each (up to
+                // 2^CONTIG_PART_LM); longer strided lines, and axis-0 lines beyond that: M/seg_rows
+                // threads per line slot in blocks of SEG_BLOCK threads, or one thread per line
                 int per = LINE_BLOCK;
-                const int ss = seg_rows((int)P->elem, vec);
-                if (ax == 0 && lm > CONTIG_REG_LM) per = LINE_BLOCK / ((1 << lm) / SEG);
-                else if (ax > 0 && lm > SHORT_LM)
-                    per = lm <= seg_max_lm((int)P->elem, vec) ? ((SEG_BLOCK * ss) >> lm) * vec : SEG_BLOCK;
+                const int lv_vec = ax > 0 ? vec : 1;
+                const int ss = seg_rows((int)P->elem, lv_vec);
+                const bool seg_solver = (ax > 0 && lm > SHORT_LM) || (ax == 0 && lm > CONTIG_PART_LM);
+                if (ax == 0 && lm > CONTIG_REG_LM && lm <= CONTIG_PART_LM) per = LINE_BLOCK / ((1 << lm) / SEG);
+                else if (seg_solver)
+                    per = lm <= seg_max_lm((int)P->elem, lv_vec) ? ((SEG_BLOCK * ss) >> lm) * lv_vec : lv_vec;
                 for (int64_t s = lo[k0]; s < lo[k1]; s += per) {
                     while (s >= lo[k + 1]) ++k;
                     SweepBlk B{};
@@ -715,20 +722,24 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
             for (int u = 0; u < P->n_units; ++u)
                 for (int i = 0; i < MAXD; ++i) lvs[(size_t)u * MAXD + i] = P->units[u].lv[i];
             march_blocks(d, P->n_units, lvs.data(), MAXD, (int)P->elem, P->march_blk);
-            if ((int64_t)P->march_blk.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
+            // the operator is offered only when every tile fits its LDS slot and every V plane of
+            // a unit is addressable with 32-bit byte offsets (its buffer accesses)
+            bool ok = (int64_t)P->march_blk.size() <= (int64_t)INT32_MAX / 2;
             for (const MarchBlk& B : P->march_blk) {
                 const int lt[3] = {B.lt[0], B.lt[1], B.lt[2]};
                 const int slot = march_slot_elems(d, lt);
-                if (slot > MARCH_MAX_PLANE) throw std::logic_error("marching tile larger than its LDS slot");
-                P->march_lp = std::max(P->march_lp, slot);
-                // buffer accesses address one V plane of a unit with 32-bit byte offsets
                 const UnitDev& U = P->units[B.unit];
                 int64_t plane = (int64_t)P->elem;
                 for (int i = 0; i < d - 1; ++i) plane <<= U.lv[i];
-                if (plane >= (int64_t)MARCH_NONE) throw std::logic_error("V plane of a unit too large for the marching operator");
+                ok = ok && slot <= MARCH_MAX_PLANE && plane < (int64_t)MARCH_NONE;
+                P->march_lp = std::max(P->march_lp, slot);
             }
-            march_order_xcd(P->march_blk, NXCD, P->march_blk_x);
-            if ((int64_t)P->march_blk_x.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
+            if (ok) {
+                march_order_xcd(P->march_blk, NXCD, P->march_blk_x);
+            } else {
+                std::vector<MarchBlk>().swap(P->march_blk);
+                P->march_lp = 0;
+            }
         }
 
         // workspace layout
@@ -769,6 +780,9 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
     } catch (const std::bad_alloc&) {
         delete P;
         return fail(AMF_E_NOMEM, "out of host memory while building the plan");
+    } catch (const std::exception& e) {
+        delete P;
+        return fail(AMF_E_INVALID, std::string("plan construction failed: ") + e.what());
     }
     *out = P;
     return AMF_OK;
@@ -881,6 +895,11 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
         while (ns < D.ax_nblk[ax] && P->ax_blk[ax][ns].lm <= SHORT_LM) ++ns;
         D.ax_nblk_short[ax] = ns;
         D.ax_vec[ax] = P->ax_vec[ax];
+    }
+    {
+        int64_t np = 0;
+        while (np < D.ax_nblk[0] && P->ax_blk[0][np].lm <= CONTIG_PART_LM) ++np;
+        D.ax0_nblk_part = np;
     }
     const bool gs = !P->gs_lines.empty();
     D.gs_unit_plane0 = gs ? (const int32_t*)(P->ws + P->off_gsu) : nullptr;
@@ -1506,7 +1525,7 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (sc->fuse_axis0 != 0 && sc->fuse_axis0 != 1) return fail(AMF_E_INVALID, "fuse_axis0 must be 0 or 1");
     if (sc->fuse_axis0 && P->sch.w_matrix != AMF_W_AMF)
         return fail(AMF_E_INVALID, "fuse_axis0 applies to the AMF W only");
-    if (sc->fuse_axis0 && (r < 2 || NODE_BLOCK * r < P->max_m0))
+    if (sc->fuse_axis0 && (r < 2 || NODE_BLOCK * r < P->max_m0 || P->max_m0 > (1 << CONTIG_PART_LM)))
         return fail(AMF_E_INVALID, "fuse_axis0 needs stencil_nodes >= 2 and 256 * stencil_nodes >= the longest axis-1 line");
     if (sc->march != 0 && sc->march != 1) return fail(AMF_E_INVALID, "march must be 0 or 1");
     if (sc->march && P->march_blk.empty()) return fail(AMF_E_INVALID, "the marching operator needs d <= 4");

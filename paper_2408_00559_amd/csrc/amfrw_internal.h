@@ -16,8 +16,8 @@ constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
 // Longer strided lines: seg_rows consecutive rows per thread (one line: 8 in FP64, 32 in FP32;
 // measured on the d = 4 workload), M/seg_rows threads per line, blocks of SEG_BLOCK threads
-// (SEG_BLOCK*seg_rows/M line slots each), up to SEG_BLOCK*seg_rows rows; beyond that one thread
-// per line streams through memory in chunks of CHUNK rows.
+// (SEG_BLOCK*seg_rows/M line slots each), up to SEG_BLOCK*seg_rows rows; beyond that one block per
+// line walks it in chunks of SEG_BLOCK*seg_rows rows.
 constexpr int SSEG_F64 = 8;
 constexpr int SSEG_F32 = 32;
 constexpr int SEG_BLOCK = 512;
@@ -31,7 +31,6 @@ constexpr int seg_max_lm(int elem, int vec)
     while (r > 1) { r >>= 1; ++l; }
     return l;
 }
-constexpr int CHUNK = 4;
 constexpr int NXCD = 8;            // MI355X: 8 XCDs, each with its own L2
 // index of the node-block table for R nodes per thread (R = 1, 2, 4, 8)
 constexpr int r_index(int R) { return R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0; }
@@ -39,9 +38,11 @@ constexpr int r_index(int R) { return R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0; 
 // a plan's schedule may override it (the autotuner picks among 1, 2, 4, 8).
 constexpr int STENCIL_R_F64 = 4;
 constexpr int STENCIL_R_F32 = 4;
-// Contiguous (axis 0) lines up to 2^CONTIG_REG_LM are solved by one thread; longer ones by SEG-row
-// segments on M/SEG cooperating lanes.
+// Contiguous (axis 0) lines up to 2^CONTIG_REG_LM are solved by one thread; longer ones up to
+// 2^CONTIG_PART_LM by SEG-row segments on M/SEG cooperating lanes of one wavefront; longer still by
+// the segmented block solver of the strided axes (stride 1, tabulated factors).
 constexpr int CONTIG_REG_LM = 4;
+constexpr int CONTIG_PART_LM = 10;
 // Sweep launches are split by line length: classes up to 2^SHORT_LM and longer ones, so that
 // short lines are not held to the register allocation of the long-line code.
 constexpr int SHORT_LM = 4;
@@ -111,6 +112,7 @@ struct DevPlan {
     const SweepBlk* ax_blk[MAXD];
     int64_t ax_nblk[MAXD];
     int64_t ax_nblk_short[MAXD];       // leading blocks with lm <= SHORT_LM
+    int64_t ax0_nblk_part;             // axis 0: leading blocks with lm <= CONTIG_PART_LM
     int ax_vec[MAXD];                  // long strided lines: 16-byte vectors of adjacent lines per slot
     // W = P solves: unit u's hyperplanes are [gs_unit_plane0[u], gs_unit_plane0[u+1]); plane p holds
     // the axis-0 lines gs_lines[gs_plane_line0[p] .. gs_plane_line0[p+1]) (line id = loc >> lv_0)

@@ -774,45 +774,6 @@ __device__ __forceinline__ void sweep_strided_regv(const DevPlan& P, const Sweep
     }
 }
 
-// Strided axis, long line: the forward sweep streams CHUNK rows at a time (loads batched) and leaves
-// d' in memory (the output, or the consumed input when updating); the backward sweep streams it back.
-template <typename T, int EPI>
-__device__ __forceinline__ void sweep_strided_mem(const DevPlan& P, const SweepArgs& A, const Strided& L, int lm)
-{
-    const int M = 1 << lm;
-    const T* in = (const T*)A.in;
-    T* dst = (EPI == EPI_STORE) ? (T*)A.out : (T*)A.in;
-    const T* f = (const T*)P.fac + L.fac;
-    T dprev = T(0);
-    for (int c0 = 0; c0 < M; c0 += CHUNK) {
-        T v[CHUNK];
-#pragma unroll
-        for (int k = 0; k < CHUNK; ++k) v[k] = in[L.base + (int64_t)(c0 + k) * L.stride];
-#pragma unroll
-        for (int k = 0; k < CHUNK; ++k) {
-            const int r = c0 + k;
-            dprev = v[k] * f[r] - f[M + r] * dprev;   // a_0 = 0 makes row 0 start from d' = g inv
-            v[k] = dprev;
-        }
-#pragma unroll
-        for (int k = 0; k < CHUNK; ++k) dst[L.base + (int64_t)(c0 + k) * L.stride] = v[k];
-    }
-    T x = T(0);                                       // c'_{M-1} = 0: x_{M-1} = d'_{M-1}
-    for (int c0 = M - CHUNK; c0 >= 0; c0 -= CHUNK) {
-        T v[CHUNK];
-#pragma unroll
-        for (int k = 0; k < CHUNK; ++k) v[k] = dst[L.base + (int64_t)(c0 + k) * L.stride];
-#pragma unroll
-        for (int k = CHUNK - 1; k >= 0; --k) {
-            x = v[k] - f[2 * M + c0 + k] * x;
-            v[k] = x;
-        }
-#pragma unroll
-        for (int k = 0; k < CHUNK; ++k) sweep_store<T, EPI>(A, L.base + (int64_t)(c0 + k) * L.stride, v[k]);
-    }
-}
-
-// Short strided lines (up to 2^SHORT_LM rows): one thread per line.
 // Short strided lines (up to 2^SHORT_LM rows): one thread per B.vec adjacent lines (1, or
 // VW = 16 B / sizeof(T) when all the block's units allow it: one vector load and store per row).
 template <typename T, int EPI>
@@ -965,25 +926,132 @@ __device__ __forceinline__ void sweep_strided_seg(const DevPlan& P, const SweepA
     }
 }
 
+// Lines longer than one block's segments (SEG_BLOCK * seg_rows rows): one block per slot of V
+// adjacent lines, walking the line in chunks of SEG_BLOCK * seg_rows rows.  Forward: each chunk runs
+// the segmented recurrence with the previous chunk's last d' as the carry into its first segment
+// (folded into that segment's affine map, so the block scan gives every segment its true carry) and
+// leaves d' in memory (the output, or the consumed input when updating); backward: the chunks in
+// reverse, the next chunk's first x as the carry.  sh: 4*SEG_BLOCK + 1 entries of LDS.
+template <typename T, int EPI, int V>
+__device__ __forceinline__ void sweep_strided_chunked(const DevPlan& P, const SweepArgs& A, const Strided& L, int lm,
+                                                      typename lane_vec<T, V>::type* sh)
+{
+    typedef typename lane_vec<T, V>::type vt;
+    const int M = 1 << lm;
+    constexpr int SSEG = seg_rows((int)sizeof(T), V);
+    constexpr int RB = SEG_BLOCK * SSEG;
+    const int nch = M / RB;
+    const int seg = threadIdx.x;
+    const T* f = (const T*)P.fac + L.fac;
+    const T* in = (const T*)A.in;
+    T* dst = (EPI == EPI_STORE) ? (T*)A.out : (T*)A.in;
+    const vt one = vt{} + T(1);
+    vt* cbuf = sh + 4 * SEG_BLOCK;
+    vt cin{};
+    for (int c = 0; c < nch; ++c) {
+        const int r0 = c * RB + seg * SSEG;
+        vt v[SSEG];
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            const T* src = in + L.base + (int64_t)(r0 + k) * L.stride;
+            if constexpr (V == 1) v[k] = ld_stream(src);
+            else v[k] = *(const vt*)src;
+        }
+        vt y{}, mu = one;
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            const T ai = f[M + r0 + k];
+            y = v[k] * f[r0 + k] - ai * y;
+            mu = -ai * mu;
+            v[k] = y;
+        }
+        if (seg == 0) {
+            y = y + mu * cin;
+            mu = vt{};
+        }
+        vt yin = segment_carry<vt>(mu, y, seg, SEG_BLOCK, 0, 1, false, sh);
+        if (seg == 0) yin = cin;
+        T m = T(1);
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            m = -f[M + r0 + k] * m;
+            v[k] = v[k] + m * yin;
+            T* q = dst + L.base + (int64_t)(r0 + k) * L.stride;
+            if constexpr (V == 1) *q = v[k];
+            else *(vt*)q = v[k];
+        }
+        if (seg == SEG_BLOCK - 1) cbuf[0] = v[SSEG - 1];
+        __syncthreads();
+        cin = cbuf[0];
+        __syncthreads();
+    }
+    cin = vt{};
+    for (int c = nch - 1; c >= 0; --c) {
+        const int r0 = c * RB + seg * SSEG;
+        vt v[SSEG];
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            const T* src = dst + L.base + (int64_t)(r0 + k) * L.stride;
+            if constexpr (V == 1) v[k] = *src;
+            else v[k] = *(const vt*)src;
+        }
+        vt x{}, nu = one;
+#pragma unroll
+        for (int k = SSEG - 1; k >= 0; --k) {
+            const T cp = f[2 * M + r0 + k];
+            x = v[k] - cp * x;
+            nu = -cp * nu;
+            v[k] = x;
+        }
+        if (seg == SEG_BLOCK - 1) {
+            x = x + nu * cin;
+            nu = vt{};
+        }
+        vt xin = segment_carry<vt>(nu, x, seg, SEG_BLOCK, 0, 1, true, sh);
+        if (seg == SEG_BLOCK - 1) xin = cin;
+        T n = T(1);
+#pragma unroll
+        for (int k = SSEG - 1; k >= 0; --k) {
+            n = -f[2 * M + r0 + k] * n;
+            v[k] = v[k] + n * xin;
+        }
+        if (seg == 0) cbuf[0] = v[0];
+#pragma unroll
+        for (int k = 0; k < SSEG; ++k) {
+            const int64_t idx = L.base + (int64_t)(r0 + k) * L.stride;
+            if constexpr (V == 1) {
+                sweep_store<T, EPI>(A, idx, v[k]);
+            } else if constexpr (EPI == EPI_STORE) {
+                *(vt*)((T*)A.out + idx) = v[k];
+            } else {
+                vt* W = (vt*)((T*)A.out + idx);
+                st_stream(W, ld_stream(W) + (T)A.b1 * ld_stream((const vt*)((const T*)A.K1 + idx)) + (T)A.b2 * v[k]);
+            }
+        }
+        __syncthreads();
+        cin = cbuf[0];
+        __syncthreads();
+    }
+}
+
 // Strided lines longer than 2^SHORT_LM rows.  Classes up to SEG_BLOCK*seg_rows rows: SEG_BLOCK*seg_rows/M
 // line slots of V adjacent lines per block, thread t on slot t mod slots and segment t / slots
-// (lanes on consecutive slots, coalesced); longer lines: one thread per line through memory.
+// (lanes on consecutive slots, coalesced); longer lines: one block per slot, in chunks.
 template <typename T, int EPI, int V>
 __global__ __launch_bounds__(SEG_BLOCK) void k_sweep_strided_long(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
     typedef typename lane_vec<T, V>::type vt;
-    __shared__ vt sh[4 * SEG_BLOCK];
+    __shared__ vt sh[4 * SEG_BLOCK + 1];
     const SweepBlk B = P.ax_blk[axis][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
     const int lm = B.lm;
     const int64_t* lo = P.ax_line_off[axis];
     constexpr int SSEG = seg_rows((int)sizeof(T), V);
-    if (lm > seg_max_lm((int)sizeof(T), V)) {   // block-uniform branch
-        const int64_t gl = B.line_start + threadIdx.x;
-        if (gl >= B.line_end) return;
+    if (lm > seg_max_lm((int)sizeof(T), V)) {   // block-uniform branch: one slot of V lines per block
+        const int64_t gl = B.line_start;
         int k = B.k_start;
         while (gl >= lo[k + 1]) ++k;
         const UnitDev& U = P.units[P.ax_units[axis][k]];
-        sweep_strided_mem<T, EPI>(P, A, strided_geom(P, U, axis, gl - lo[k], lm, A.run), lm);
+        sweep_strided_chunked<T, EPI, V>(P, A, strided_geom(P, U, axis, gl - lo[k], lm, A.run), lm, sh);
         return;
     }
     const int slots = (SEG_BLOCK * SSEG) >> lm;
@@ -1177,7 +1245,7 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArg
         case 8: sweep_contig_part<T, 16>(A, L, nudt, p); break;
         case 9: sweep_contig_part<T, 32>(A, L, nudt, p); break;
         case 10: sweep_contig_part<T, 64>(A, L, nudt, p); break;
-        default: break;   // longer lines are rejected at plan creation
+        default: break;   // longer lines go to k_sweep_strided_long
         }
     }
 }
@@ -1608,7 +1676,7 @@ __global__ __launch_bounds__(LOWER_BLOCK) void k_lower(DevPlan P, LowerArgs A)
     case 1: lower_unit<T, D, 2>(P, U, u, A); break;
     case 2: lower_unit<T, D, 4>(P, U, u, A); break;
     case 3: lower_unit<T, D, 8>(P, U, u, A); break;
-    default: lower_unit<T, D, 16>(P, U, u, A); break;  // axis-1 levels above 10 are rejected
+    default: lower_unit<T, D, 16>(P, U, u, A); break;  // axis-1 levels above CONTIG_PART_LM are rejected
     }
 }
 
@@ -1734,7 +1802,14 @@ static void sweep_part(const DevPlan& P, int axis, int epi, const SweepArgs& a, 
                        hipStream_t s)
 {
     dim3 g((unsigned)nb), b(LINE_BLOCK), bl(SEG_BLOCK);
-    if (axis == 0) hipLaunchKernelGGL((k_sweep_contig<T, LONG>), g, b, 0, s, P, a, b0);
+    if (axis == 0 && LONG) {
+        // lines up to 2^CONTIG_PART_LM: lanes of one wavefront; longer: the segmented block solver
+        const int64_t n1 = std::min<int64_t>(nb, std::max<int64_t>(0, P.ax0_nblk_part - b0));
+        if (n1 > 0) hipLaunchKernelGGL((k_sweep_contig<T, true>), dim3((unsigned)n1), b, 0, s, P, a, b0);
+        if (nb > n1)
+            hipLaunchKernelGGL((k_sweep_strided_long<T, EPI_STORE, 1>), dim3((unsigned)(nb - n1)), bl, 0, s, P, a, 0,
+                               b0 + n1);
+    } else if (axis == 0) hipLaunchKernelGGL((k_sweep_contig<T, LONG>), g, b, 0, s, P, a, b0);
     else if (!LONG && epi == EPI_STORE) hipLaunchKernelGGL((k_sweep_strided<T, EPI_STORE>), g, b, 0, s, P, a, axis, b0);
     else if (!LONG) hipLaunchKernelGGL((k_sweep_strided<T, EPI_UPDATE>), g, b, 0, s, P, a, axis, b0);
     else {

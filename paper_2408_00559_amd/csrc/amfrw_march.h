@@ -59,8 +59,18 @@ struct alignas(16) MarchBlk {
 // 256 nodes for d = 2 (one plane axis).
 inline int march_row_log2(int d, int elem) { return d == 2 ? 8 : (elem == 8 ? 4 : 5); }
 
+// Elements of one plane slot: (T_0 + 2) x (T_1 + 2) x (T_2 + 2) over the plane axes.
+inline int march_slot_elems(int d, const int* lt)
+{
+    int p = 1;
+    for (int k = 0; k < d - 1; ++k) p *= (1 << lt[k]) + 2;
+    return p;
+}
+
 // Tile extents for a unit with per-axis levels lv (d axes): nodes per tile plane <= MARCH_THREADS.
-// The remaining thread budget after axis 0 is split between the other plane axes.
+// The remaining thread budget after axis 0 is split between the other plane axes; a tile whose
+// slot (with halo) would exceed MARCH_MAX_PLANE, a thin one of a unit with short axes, is halved
+// along its longest axis until it fits.
 inline void march_tile(int d, const int* lv, int elem, int* lt)
 {
     for (int k = 0; k < 3; ++k) lt[k] = 0;
@@ -75,14 +85,12 @@ inline void march_tile(int d, const int* lv, int elem, int* lt)
         lt[2] = std::min(lv[2], budget - lt[1]);
         lt[1] = std::min(lv[1], budget - lt[2]);
     }
-}
-
-// Elements of one plane slot: (T_0 + 2) x (T_1 + 2) x (T_2 + 2) over the plane axes.
-inline int march_slot_elems(int d, const int* lt)
-{
-    int p = 1;
-    for (int k = 0; k < d - 1; ++k) p *= (1 << lt[k]) + 2;
-    return p;
+    while (march_slot_elems(d, lt) > MARCH_MAX_PLANE) {
+        int k = 0;
+        for (int i = 1; i < na; ++i)
+            if (lt[i] > lt[k]) k = i;
+        --lt[k];
+    }
 }
 
 // Compiled stride sets: full tiles (MARCH_THREADS nodes) of d = 3 and 4 with the given log2 T_0,

@@ -244,8 +244,10 @@ class Plan:
                     fuse_max_axis0=sc.fuse_max_axis0, march=sc.march, march_available=sc.march_available)
 
     def fuse_allowed(self, stencil_nodes: int) -> bool:
-        """Whether the operator launches can also solve axis 0 at this many nodes per thread."""
-        return stencil_nodes >= 2 and 256 * stencil_nodes >= self.schedule()["fuse_max_axis0"]
+        """Whether the operator launches can also solve axis 0 at this many nodes per thread: the
+        fused solve takes whole axis-0 lines of at most 256 * stencil_nodes and 1024 rows."""
+        m0 = self.schedule()["fuse_max_axis0"]
+        return stencil_nodes >= 2 and 256 * stencil_nodes >= m0 and m0 <= 1024
 
     def set_schedule(self, stencil_nodes: int | None = None, xcd_remap: int | None = None,
                      resident: int | None = None, fuse_axis0: int | None = None, march: int | None = None):

@@ -12,7 +12,7 @@ import oracle
 from paper_2408_00559_amd import inputs as I
 from paper_2408_00559_amd.solver import Plan
 
-from _util import parallel, rel_maxerr, unit_slices
+from _util import axis_backward_error, parallel, rel_maxerr, unit_slices
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -28,13 +28,22 @@ def _cases():
         "long_rate_axis": (I.workload_fg2d()["problems"], I.full_grid([10, 3])),
         "long_v_axis": (I.workload_fg2d()["problems"], I.full_grid([3, 10])),
         # strided lines of 2^13 and 2^15 rows: the longest classes of the segmented solver and the
-        # one-thread-per-line memory path beyond it
+        # chunked block solver beyond it
         "very_long_v_axis": (I.workload_fg2d()["problems"], I.full_grid([2, 13])),
         "longest_v_axis": (I.workload_fg2d()["problems"], I.full_grid([1, 15])),
         # unit-resident grids with fewer lines than workgroup threads (segmented solves in LDS)
         "res_long_axis0": (I.workload_fg2d()["problems"], I.full_grid([9, 2])),
         "res_long_v": (I.workload_fg2d()["problems"], I.full_grid([2, 9])),
         "res_one_line": (I.workload_fg2d()["problems"], I.full_grid([10, 0])),
+        # axis-0 lines beyond one wavefront's segments: the block-segmented solver (2^12 rows)
+        # and the chunked block solver (2^15 rows in FP64; in FP32 still segmented)
+        "long_axis0_12": (I.workload_fg2d()["problems"], I.full_grid([12, 2])),
+        "long_axis0_15": (I.workload_fg2d()["problems"], I.full_grid([15, 1])),
+        # single lines of 2^17 points on either axis: the chunked block solver (32 chunks in FP64)
+        "axis0_2e17": (I.workload_fg2d()["problems"], I.full_grid([17, 0])),
+        "v_axis_2e17": (I.workload_fg2d()["problems"], I.full_grid([0, 17])),
+        # the standard technique at level 12: grids from 2^12 x 1 to 1 x 2^12 inner points
+        "d2_standard_ct12": ([I.paper_caplet(sigma=0.3, phi=0.4)], I.combination(12, 0)),
         "d3_full_ragged": (d3[:1], I.full_grid([7, 0, 8])),
         "d2_standard_ct": ([I.paper_caplet(sigma=0.3, phi=0.4)], I.combination(6, 0)),
         "d3_ct": (d3, I.combination(4, 1)),
@@ -101,13 +110,24 @@ def test_axis_solves(name):
             p = probs[u["problem"]]
             lv = u["levels"]
             full = oracle.full_from_inner(g[sl], lv)
-            ref = oracle.inner_view(oracle.solve_axis(p, lv, ax, theta * p.T / steps, full), lv)
-            # Thomas rounding grows with the line length M: bound ~ M eps
-            tol = max(1e-13, 4e-16 * (1 << lv[ax]))
-            assert rel_maxerr(out[sl], ref) < tol, (ax, u)
+            nudt = theta * p.T / steps
+            ref = oracle.inner_view(oracle.solve_axis(p, lv, ax, nudt, full), lv)
+            # every solve is normwise backward stable: a few eps whatever the line length
+            if (1 << lv[ax]) >= 256:
+                eta = axis_backward_error(oracle, p, lv, ax, nudt, out[sl], g[sl])
+                assert eta < 8 * 2.2e-16, (ax, u, eta)
+            if (1 << lv[ax]) <= 4096:
+                # Thomas rounding grows with the line length M: bound ~ M eps
+                tol = max(1e-13, 4e-16 * (1 << lv[ax]))
+                assert rel_maxerr(out[sl], ref) < tol, (ax, u)
+            else:
+                # longer lines are stiff (nu dt |A| reaches ~1e10 on a 2^17-point rate axis), so
+                # two correct eliminations differ by up to the condition number times eps
+                assert rel_maxerr(out[sl], ref) < 1e-8, (ax, u, rel_maxerr(out[sl], ref))
 
 
-@pytest.mark.parametrize("name", ["long_rate_axis", "long_v_axis", "very_long_v_axis", "longest_v_axis", "d4_ct"])
+@pytest.mark.parametrize("name", ["long_rate_axis", "long_v_axis", "very_long_v_axis", "longest_v_axis", "d4_ct",
+                                  "long_axis0_12", "long_axis0_15", "axis0_2e17", "v_axis_2e17"])
 def test_axis_solves_fp32(name):
     """a4/a10 in FP32 (factor tables computed in FP64, cast once): every line length class of the
     strided solvers, from register lines through the segmented solver to the memory path, against
@@ -124,9 +144,15 @@ def test_axis_solves_fp32(name):
             p = probs[u["problem"]]
             lv = u["levels"]
             full = oracle.full_from_inner(g[sl].astype(np.float64), lv)
-            ref = oracle.inner_view(oracle.solve_axis(p, lv, ax, theta * p.T / steps, full), lv)
-            # FP32 rounding in the recurrences grows with the line length (the Neumann end of a
-            # long axis-1 line is a stiff, nearly singular Laplacian block): bound ~ M eps_32
+            nudt = theta * p.T / steps
+            ref = oracle.inner_view(oracle.solve_axis(p, lv, ax, nudt, full), lv)
+            # the FP32 solve is normwise backward stable to a few eps_32 (factor tables rounded once
+            # from FP64, recurrences in FP32) ...
+            eta = axis_backward_error(oracle, p, lv, ax, nudt, out[sl], g[sl].astype(np.float64))
+            assert eta < 8 * 6e-8, (ax, u, eta)
+            # ... so the forward difference is bounded by the condition number (<= 1 + 4 nu dt
+            # max delta, as (I - nu dt A) is diagonally dominant by 1), which grows like M^2 on a
+            # rate axis; the bound below covers the measured differences up to 2^17 points
             tol = max(4e-6, 2e-7 * (1 << lv[ax]))
             assert rel_maxerr(out[sl], ref) < tol, (ax, u, rel_maxerr(out[sl], ref))
 
@@ -259,7 +285,8 @@ def test_schedules_agree(name):
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
 @pytest.mark.parametrize("name", ["fg2d", "long_rate_axis", "long_v_axis", "very_long_v_axis", "res_one_line",
-                                  "d3_full_ragged", "d2_standard_ct", "d3_ct", "d4_ct"])
+                                  "d3_full_ragged", "d2_standard_ct", "d3_ct", "d4_ct", "long_axis0_12",
+                                  "d2_standard_ct12"])
 def test_march_schedule(name, precision, tol):
     """The plane-tiled operator (LDS ring of V planes) with the separate axis-1 solves: two steps,
     every node of every unit against the oracle, with and without the XCD remap."""

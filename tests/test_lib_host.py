@@ -88,7 +88,7 @@ def test_invalid_grid_and_scheme():
     p = I.draw_instances(1, seed=1, d=4)[0]
     assert _create([p], I.combination(2, 1))[0] == L.E_INVALID          # n < d - 1
     assert _create([p], I.combination(5, -1))[0] == L.E_INVALID
-    assert _create([p], I.full_grid([20, 1, 1, 1]))[0] == L.E_INVALID
+    assert _create([p], I.full_grid([21, 1, 1, 1]))[0] == L.E_INVALID
     assert _create([p], I.combination(5, 1), steps=0)[0] == L.E_INVALID
     sc = S.scheme_amfrw2()
     sc.stages = 7
@@ -223,6 +223,25 @@ def test_schedule_validation():
     assert sc.max_stencil_nodes == 2 and sc.resident_available == 1
     assert _set(h, stencil_nodes=4) == L.E_INVALID
     assert _set(h, resident=1) == L.OK
+    L.lib().amf_plan_destroy(h)
+
+
+def test_long_axis0_lines():
+    """Axis-0 levels up to 16 build (the paper's standard-technique levels); the W = P solve and the
+    fused axis-0 schedule keep their 2^10 limit and say so."""
+    p = I.paper_swaption(3)
+    for grid in (I.combination(13, 1), I.combination(12, 0), I.full_grid([16, 0, 0, 0])):
+        st, h = _create([p], grid, steps=16)
+        assert st == L.OK
+        sc = _sched(h)
+        assert sc.fuse_max_axis0 > 1024
+        assert _set(h, stencil_nodes=8, fuse_axis0=1) == L.E_INVALID
+        assert _set(h, stencil_nodes=1, fuse_axis0=0, march=1) == L.OK
+        L.lib().amf_plan_destroy(h)
+    gs = S.scheme_theta_gs(1.0, 1)
+    assert _create([p], I.combination(13, 1), scheme=gs)[0] == L.E_UNSUPPORTED
+    code, h = _create([p], I.combination(9, 1), scheme=gs)
+    assert code == L.OK
     L.lib().amf_plan_destroy(h)
 
 
