@@ -20,12 +20,17 @@ sys.path.insert(0, ROOT)
 METRIC = ("grid-point stage-updates/s and prices/s at 1e-5 rel err, plain FP64 vs batched "
           "FP32/surrogate")
 HBM_PEAK_GBPS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2408_00559_amd", "csrc", "amfrw_kernels.hip")
+KERNEL_SRC = [os.path.join(ROOT, "paper_2408_00559_amd", "csrc", f)
+              for f in ("amfrw_kernels.hip", "amfrw_march.h", "amfrw_internal.h", "amfrw_consts.h")]
 GOLDEN = os.path.join(ROOT, "tests", "golden", "ct4_n7_psi3_fp64.json")
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the device code's sources (kernels and the headers they include)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 COPY_BYTES = 2 << 30
@@ -41,6 +46,9 @@ def kernel_class_of(name: str):
             return ("sweep_update" if up else "sweep_strided") + ("_long" if lg else "")
     if "k_sweep_contig<" in name:
         return "sweep_contig_long" if "true>" in name else "sweep_contig"
+    if "k_march<" in name:    # template arguments <T, D, OP>
+        op = name.split("k_march<", 1)[1].split(">", 1)[0].split(",")[2].strip()
+        return {"2": "stage1", "3": "stage2", "4": "refine"}[op]
     for sym in ("k_stencil_vec<", "k_stencil<"):
         if sym in name:       # template arguments <T, D, OP[, R]>
             op = name.split(sym, 1)[1].split(">", 1)[0].split(",")[2].strip()
@@ -504,6 +512,7 @@ def main():
     ap.add_argument("--no-ct6", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
+    ap.add_argument("--no-fg2d", action="store_true")
     ap.add_argument("--only", choices=["serving", "ct6", "surrogate", "fg2d", "paper"], default=None,
                     help="run one secondary section alone and print its JSON (profiling runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -581,7 +590,8 @@ def main():
                        "rel_err_against": "oracle" if ref else "fp64 GPU",
                        "roofline": f32["roofline"], "kernels": f32["kernels"],
                        "schedule": f32["schedule"], "autotune": f32["autotune"]}
-    res["fg2d_65x65"] = run_fg2d(torch, Plan)
+    if not args.no_fg2d:
+        res["fg2d_65x65"] = run_fg2d(torch, Plan)
     if not args.no_serving:
         res["serving_batch4"] = run_serving(torch, Plan)
     if not args.no_ct6:

@@ -226,7 +226,7 @@ class Plan:
     def axis_solve(self, axis: int, x: torch.Tensor, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
         assert x.dtype == self.dtype and x.numel() == self.vector_len and x.is_contiguous()
         if out is None:
-            out = torch.empty_like(x)
+            out = torch.zeros_like(x)          # the padding between units is never written
         L.check(L.lib().amf_axis_solve(self._h, int(axis), C.c_void_p(x.data_ptr()),
                                        C.c_void_p(out.data_ptr()), _stream(stream)))
         return out
