@@ -58,6 +58,9 @@ struct amf_plan {
     std::vector<ProbDev> probdev;
     std::vector<int32_t> blk_unit;
     std::vector<int32_t> blk_unit_r[4];    // node blocks of NODE_BLOCK * {1, 2, 4, 8} nodes
+    std::vector<VecBlk> vblk;              // operator blocks by axis-1 line class (VB_LISTS lists)
+    int64_t vblk_off[VB_LISTS]{}, vblk_n[VB_LISTS]{};
+    size_t off_vblk = 0;
     int stencil_r = 1, min_m0 = 1, max_m0 = 1, xcd = 1;
     int fuse0 = 0;                         // fused axis-0 solve in the operator launches
     bool res_ok = false;                   // every unit fits the unit-resident schedule
@@ -562,6 +565,32 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         };
         block_table(NODE_BLOCK, P->blk_unit);
         for (int k = 0; k < 4; ++k) block_table((int64_t)NODE_BLOCK << k, P->blk_unit_r[k]);
+        // operator blocks of R nodes per thread over the runs of consecutive units of one axis-1
+        // line class; unit offsets are multiples of min(M_1, 1024) >= R, so every thread's R
+        // nodes lie on one line
+        auto vb_list = [&](int id, int R, auto pred) {
+            P->vblk_off[id] = (int64_t)P->vblk.size();
+            const int64_t per = (int64_t)NODE_BLOCK * R;
+            for (int u = 0; u < P->n_units;) {
+                if (!pred(u)) {
+                    ++u;
+                    continue;
+                }
+                int v = u;
+                while (v < P->n_units && pred(v)) ++v;
+                const int64_t g1 = P->units[v - 1].off + ((int64_t)1 << P->units[v - 1].lsum);
+                int w = u;
+                for (int64_t g = P->units[u].off; g < g1; g += per) {
+                    while (P->units[w + 1].off <= g) ++w;
+                    P->vblk.push_back(VecBlk{g, g1, (int32_t)w, 0});
+                }
+                u = v;
+            }
+            P->vblk_n[id] = (int64_t)P->vblk.size() - P->vblk_off[id];
+        };
+        for (int R = 1; R <= 4; R *= 2) vb_list(vb_exact(R), R, [&](int u) { return P->units[u].lv[0] == (R == 1 ? 0 : R == 2 ? 1 : 2); });
+        for (int R = 1; R <= 8; R *= 2) vb_list(vb_atleast(R), R, [&](int u) { return (1 << P->units[u].lv[0]) >= R; });
+        if ((int64_t)P->vblk.size() > (int64_t)INT32_MAX) throw std::bad_alloc();
         // time-loop operator: R consecutive axis-0 nodes per thread, R <= every unit's M_0
         int min_m0 = 1 << MAX_LEVEL, max_m0 = 1;
         for (int u = 0; u < P->n_units; ++u) {
@@ -576,7 +605,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                     scheme->stages == 2 && scheme->w_matrix == AMF_W_AMF;
         P->res_lds_len = (1 << max_lsum) + ((1 << max_lsum) >> 4);
         const int rmax = precision == AMF_FP64 ? STENCIL_R_F64 : STENCIL_R_F32;
-        P->stencil_r = std::min(rmax, min_m0) >= 4 ? 4 : (std::min(rmax, min_m0) >= 2 ? 2 : 1);
+        P->stencil_r = rmax;                   // each unit runs at min(stencil_r, M_1)
         // per axis (one host thread each): units ordered by M_axis, line offsets, blocks that
         // never mix line lengths
         auto build_axis = [&](int ax) {
@@ -760,6 +789,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         P->off_fac = take(P->facd.size() * P->elem);
         P->off_blk = take(P->blk_unit.size() * sizeof(int32_t));
         for (int k = 0; k < 4; ++k) P->off_blkr[k] = take(P->blk_unit_r[k].size() * sizeof(int32_t));
+        P->off_vblk = take(P->vblk.size() * sizeof(VecBlk));
         for (int ax = 0; ax < d; ++ax) {
             P->off_axu[ax] = take(P->ax_units[ax].size() * sizeof(int32_t));
             P->off_axl[ax] = take(P->ax_line_off[ax].size() * sizeof(int64_t));
@@ -852,6 +882,7 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
     if ((st = upload(P->ws + P->off_blk, P->blk_unit.data(), P->blk_unit.size() * 4, s))) return st;
     for (int k = 0; k < 4; ++k)
         if ((st = upload(P->ws + P->off_blkr[k], P->blk_unit_r[k].data(), P->blk_unit_r[k].size() * 4, s))) return st;
+    if ((st = upload(P->ws + P->off_vblk, P->vblk.data(), P->vblk.size() * sizeof(VecBlk), s))) return st;
     for (int ax = 0; ax < P->d; ++ax) {
         if ((st = upload(P->ws + P->off_axu[ax], P->ax_units[ax].data(), P->ax_units[ax].size() * 4, s))) return st;
         if ((st = upload(P->ws + P->off_axl[ax], P->ax_line_off[ax].data(), P->ax_line_off[ax].size() * 8, s))) return st;
@@ -885,6 +916,11 @@ amf_status bind_impl(amf_plan* P, void* d_ws, hipStream_t s)
     for (int k = 0; k < 4; ++k) {
         D.blk_unit_r[k] = (const int32_t*)(P->ws + P->off_blkr[k]);
         D.n_blocks_r[k] = (int64_t)P->blk_unit_r[k].size();
+    }
+    D.vblk = (const VecBlk*)(P->ws + P->off_vblk);
+    for (int k = 0; k < VB_LISTS; ++k) {
+        D.vblk_off[k] = P->vblk_off[k];
+        D.vblk_n[k] = P->vblk_n[k];
     }
     for (int ax = 0; ax < P->d; ++ax) {
         D.ax_units[ax] = (const int32_t*)(P->ws + P->off_axu[ax]);
@@ -1503,7 +1539,7 @@ amf_status amf_schedule_get(const amf_plan* P, amf_schedule* out)
     out->struct_size = sizeof(amf_schedule);
     out->stencil_nodes = P->stencil_r;
     out->xcd_remap = P->xcd;
-    out->max_stencil_nodes = std::min(8, P->min_m0);
+    out->max_stencil_nodes = 8;
     out->resident = P->resident;
     out->resident_available = P->res_ok ? 1 : 0;
     out->fuse_axis0 = P->fuse0;
@@ -1518,15 +1554,15 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (!P || !sc || sc->struct_size != sizeof(amf_schedule)) return fail(AMF_E_INVALID, "bad amf_schedule");
     const int r = sc->stencil_nodes;
     if (r != 1 && r != 2 && r != 4 && r != 8) return fail(AMF_E_INVALID, "stencil_nodes must be 1, 2, 4 or 8");
-    if (r > P->min_m0) return fail(AMF_E_INVALID, "stencil_nodes exceeds the smallest axis-1 line");
     if (sc->xcd_remap < 0 || sc->xcd_remap > 2) return fail(AMF_E_INVALID, "xcd_remap must be 0, 1 or 2");
     if (sc->resident != 0 && sc->resident != 1) return fail(AMF_E_INVALID, "resident must be 0 or 1");
     if (sc->resident && !P->res_ok) return fail(AMF_E_INVALID, "a unit exceeds the unit-resident size limit");
     if (sc->fuse_axis0 != 0 && sc->fuse_axis0 != 1) return fail(AMF_E_INVALID, "fuse_axis0 must be 0 or 1");
     if (sc->fuse_axis0 && P->sch.w_matrix != AMF_W_AMF)
         return fail(AMF_E_INVALID, "fuse_axis0 applies to the AMF W only");
-    if (sc->fuse_axis0 && (r < 2 || NODE_BLOCK * r < P->max_m0 || P->max_m0 > (1 << CONTIG_PART_LM)))
-        return fail(AMF_E_INVALID, "fuse_axis0 needs stencil_nodes >= 2 and 256 * stencil_nodes >= the longest axis-1 line");
+    if (sc->fuse_axis0 && (r < 2 || r > P->min_m0 || NODE_BLOCK * r < P->max_m0 || P->max_m0 > (1 << CONTIG_PART_LM)))
+        return fail(AMF_E_INVALID, "fuse_axis0 needs 2 <= stencil_nodes <= the shortest axis-1 line and 256 * "
+                                   "stencil_nodes >= the longest one (at most 1024 points)");
     if (sc->march != 0 && sc->march != 1) return fail(AMF_E_INVALID, "march must be 0 or 1");
     if (sc->march && P->march_blk.empty()) return fail(AMF_E_INVALID, "the marching operator needs d <= 4");
     if (sc->march && sc->fuse_axis0) return fail(AMF_E_INVALID, "the marching operator does not fuse the axis-1 solve");

@@ -90,6 +90,18 @@ struct alignas(16) SweepBlk {
     int32_t pad_;
 };
 
+// A block of the streaming operator with R consecutive axis-1 nodes per thread, over one run of
+// consecutive units of the same line class: nodes g0 + t R, t < NODE_BLOCK, below gend.
+struct alignas(8) VecBlk {
+    int64_t g0, gend;
+    int32_t unit;         // the unit containing g0 (or whose padding holds it)
+    int32_t pad_;
+};
+// lists: units with M_1 == 1, 2, 4 (ids 0..2) and with M_1 >= 1, 2, 4, 8 (ids 3..6)
+constexpr int VB_LISTS = 7;
+constexpr int vb_exact(int R) { return R == 4 ? 2 : R == 2 ? 1 : 0; }
+constexpr int vb_atleast(int R) { return 3 + (R == 8 ? 3 : R == 4 ? 2 : R == 2 ? 1 : 0); }
+
 // Device view of a bound plan (pointers into the workspace).
 struct DevPlan {
     int d;
@@ -107,6 +119,9 @@ struct DevPlan {
     int xcd;                     // 1: XCD-aware block remapping
     const int32_t* blk_unit_r[4];   // per block of NODE_BLOCK * R nodes (R = 1, 2, 4, 8): first unit
     int64_t n_blocks_r[4];
+    // operator blocks by axis-1 line class (units with M_1 = 1, 2, 4; M_1 >= 1, 2, 4, 8)
+    const VecBlk* vblk;
+    int64_t vblk_off[VB_LISTS], vblk_n[VB_LISTS];
     const int32_t* ax_units[MAXD];     // per axis: units ordered by M_axis
     const int64_t* ax_line_off[MAXD];  // per axis: first line of each listed unit (+ sentinel)
     const SweepBlk* ax_blk[MAXD];

@@ -335,19 +335,32 @@ __device__ __forceinline__ void axis0_segment_solve(T* v, const T* f, int M0, in
 // A.S; the stage operators still write K^(0) to A.W (the refinement reads it), the refinement
 // writes only the solved values.
 template <typename T, int D, int OP, int R, bool FUSE>
-__global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilArgs A)
+__global__ __launch_bounds__(NODE_BLOCK) void k_stencil_vec(DevPlan P, StencilArgs A, int list)
 {
     static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
     const int64_t lb = xcd_block(blockIdx.x, gridDim.x, P.xcd != 0);
-    const int64_t g = (lb * NODE_BLOCK + threadIdx.x) * R;
-    bool live = g < P.total;
+    // fused: dense blocks over the whole vector (one R for the plan); else the block list of one
+    // axis-1 line class (each unit at R = min(stencil_nodes, M_1))
+    int64_t g, gend;
+    int32_t u0;
+    if constexpr (FUSE) {
+        g = (lb * NODE_BLOCK + threadIdx.x) * R;
+        gend = P.total;
+        u0 = g < P.total ? P.blk_unit_r[r_index(R)][lb] : 0;
+    } else {
+        const VecBlk B = P.vblk[P.vblk_off[list] + lb];
+        g = B.g0 + (int64_t)threadIdx.x * R;
+        gend = B.gend;
+        u0 = B.unit;
+    }
+    bool live = g < gend;
     if constexpr (!FUSE) {
         if (!live) return;
     }
     int u = 0;
     int64_t loc = 0;
     if (live) {
-        u = find_unit(P.units, P.blk_unit_r[r_index(R)][lb], g);
+        u = find_unit(P.units, u0, g);
         loc = g - P.units[u].off;
         live = loc < ((int64_t)1 << P.units[u].lsum);     // else alignment padding
     }
@@ -1716,26 +1729,38 @@ hipError_t launch_state_read(const DevPlan& P, int prec, const void* W, void* Y,
     return prec == 0 ? node_t<double, 2>(P, W, Y, s) : node_t<float, 2>(P, W, Y, s);
 }
 
+// One launch of the unfused operator over the block list `list` at R nodes per thread.
+template <typename T, int D, int R>
+static void stencil_vec_list(const DevPlan& P, int op, const StencilArgs& a, int list, hipStream_t s)
+{
+    if (P.vblk_n[list] <= 0) return;
+    dim3 g((unsigned)P.vblk_n[list]), b(NODE_BLOCK);
+    switch (op) {
+    case OP_STAGE1: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R, false>), g, b, 0, s, P, a, list); break;
+    case OP_STAGE2: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R, false>), g, b, 0, s, P, a, list); break;
+    default: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R, false>), g, b, 0, s, P, a, list); break;
+    }
+}
+
+// The streaming operator at up to R consecutive axis-1 nodes per thread.  Fused: one launch, R for
+// every unit.  Unfused: every unit at min(R, M_1), one launch per axis-1 line class present.
 template <typename T, int D, int R>
 static hipError_t stencil_vec(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
-    dim3 g((unsigned)P.n_blocks_r[r_index(R)]), b(NODE_BLOCK);
-    const bool fuse = a.S != nullptr;
-    switch (op) {
-    case OP_STAGE1:
-        if (fuse) hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R, true>), g, b, 0, s, P, a);
-        else hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R, false>), g, b, 0, s, P, a);
-        break;
-    case OP_STAGE2:
-        if (fuse) hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R, true>), g, b, 0, s, P, a);
-        else hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R, false>), g, b, 0, s, P, a);
-        break;
-    case OP_REFINE:
-        if (fuse) hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R, true>), g, b, 0, s, P, a);
-        else hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R, false>), g, b, 0, s, P, a);
-        break;
-    default: return hipErrorInvalidValue;
+    if (op != OP_STAGE1 && op != OP_STAGE2 && op != OP_REFINE) return hipErrorInvalidValue;
+    if (a.S != nullptr) {
+        dim3 g((unsigned)P.n_blocks_r[r_index(R)]), b(NODE_BLOCK);
+        switch (op) {
+        case OP_STAGE1: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE1, R, true>), g, b, 0, s, P, a, 0); break;
+        case OP_STAGE2: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_STAGE2, R, true>), g, b, 0, s, P, a, 0); break;
+        default: hipLaunchKernelGGL((k_stencil_vec<T, D, OP_REFINE, R, true>), g, b, 0, s, P, a, 0); break;
+        }
+        return hipGetLastError();
     }
+    if constexpr (R > 1) stencil_vec_list<T, D, 1>(P, op, a, vb_exact(1), s);
+    if constexpr (R > 2) stencil_vec_list<T, D, 2>(P, op, a, vb_exact(2), s);
+    if constexpr (R > 4) stencil_vec_list<T, D, 4>(P, op, a, vb_exact(4), s);
+    stencil_vec_list<T, D, R>(P, op, a, vb_atleast(R), s);
     return hipGetLastError();
 }
 

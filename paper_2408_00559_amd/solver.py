@@ -245,9 +245,12 @@ class Plan:
 
     def fuse_allowed(self, stencil_nodes: int) -> bool:
         """Whether the operator launches can also solve axis 0 at this many nodes per thread: the
-        fused solve takes whole axis-0 lines of at most 256 * stencil_nodes and 1024 rows."""
+        fused solve runs every unit at stencil_nodes (at most the shortest axis-0 line) and takes
+        whole axis-0 lines of at most 256 * stencil_nodes and 1024 rows."""
+        if not hasattr(self, "_min_m0"):
+            self._min_m0 = min(1 << u["levels"][0] for u in self.units())
         m0 = self.schedule()["fuse_max_axis0"]
-        return stencil_nodes >= 2 and 256 * stencil_nodes >= m0 and m0 <= 1024
+        return 2 <= stencil_nodes <= self._min_m0 and 256 * stencil_nodes >= m0 and m0 <= 1024
 
     def set_schedule(self, stencil_nodes: int | None = None, xcd_remap: int | None = None,
                      resident: int | None = None, fuse_axis0: int | None = None, march: int | None = None):

@@ -255,7 +255,9 @@ def test_determinism_and_restart():
 
 @pytest.mark.parametrize("name", ["fg2d", "d3_ct", "d4_ct", "d6_ct", "long_rate_axis"])
 def test_schedules_agree(name):
-    """Every launch schedule (operator nodes per thread, XCD remapping) gives the oracle's step."""
+    """Every launch schedule (operator nodes per thread, XCD remapping) gives the oracle's step.
+    Each unit runs at min(stencil_nodes, M_1), so the d = 3, 4, 6 plans (M_1 from 2 up) mix line
+    classes of 2, 4 and 8 nodes per thread within one operator call."""
     probs, grid = CASES[name]
     steps = 5
     plan = Plan(probs, grid, steps=steps, device=DEV)

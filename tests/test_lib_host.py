@@ -216,13 +216,16 @@ def test_schedule_validation():
     assert _sched(h).march_available == 0
     assert _set(h, stencil_nodes=1, march=1) == L.E_INVALID
     L.lib().amf_plan_destroy(h)
-    # a plan whose smallest axis-0 line has 2 nodes allows at most 2 nodes per thread
+    # a plan whose smallest axis-0 line has 2 nodes: every unit runs at min(stencil_nodes, M_1),
+    # but the fused solve needs stencil_nodes <= 2
     p = I.draw_instances(1, seed=9, d=3)[0]
     st, h = _create([p], I.combination(4, 1))
     sc = _sched(h)
-    assert sc.max_stencil_nodes == 2 and sc.resident_available == 1
-    assert _set(h, stencil_nodes=4) == L.E_INVALID
-    assert _set(h, resident=1) == L.OK
+    assert sc.max_stencil_nodes == 8 and sc.resident_available == 1
+    assert _set(h, stencil_nodes=8) == L.OK
+    assert _set(h, stencil_nodes=4, fuse_axis0=1) == L.E_INVALID
+    assert _set(h, stencil_nodes=2, fuse_axis0=1) == L.OK
+    assert _set(h, stencil_nodes=2, fuse_axis0=0, resident=1) == L.OK
     L.lib().amf_plan_destroy(h)
 
 
