@@ -62,7 +62,7 @@ def kernel_class_of(name: str):
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, precision: str, out_path: str, command: str):
-    """Per kernel class: mean FETCH_SIZE and WRITE_SIZE per dispatch (KiB, from two rocprofv3 --pmc
+    """Per kernel class: median FETCH_SIZE and WRITE_SIZE per dispatch (KiB, from two rocprofv3 --pmc
     runs), scaled by what the same counters read for the 2 GiB device-to-device copy."""
     import csv
     import glob
@@ -82,7 +82,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, precision: str, out_path: str,
                     per.setdefault(k, []).append(v)
         big = sorted(c for c in copies if c * 1024 > COPY_BYTES / 2)
         scale = (COPY_BYTES / 1024.0) / big[len(big) // 2] if big else None
-        return {k: sum(v) / len(v) for k, v in per.items()}, scale, len(big)
+        # median per class: the timed solves dominate the dispatch count, so the median is the
+        # tuned schedule's launch even when a few launches of other schedules precede them
+        return {k: sorted(v)[len(v) // 2] for k, v in per.items()}, scale, len(big)
 
     fetch, fs, nf = load(fetch_dir, "FETCH_SIZE")
     write, ws, nw = load(write_dir, "WRITE_SIZE")
@@ -513,6 +515,7 @@ def main():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-paper", action="store_true")
     ap.add_argument("--no-fg2d", action="store_true")
+    ap.add_argument("--serving-batches", type=int, default=200, help="timed batches of the serving section")
     ap.add_argument("--only", choices=["serving", "ct6", "surrogate", "fg2d", "paper"], default=None,
                     help="run one secondary section alone and print its JSON (profiling runs)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -536,8 +539,8 @@ def main():
     from paper_2408_00559_amd.solver import Plan
 
     if args.only:
-        run = {"serving": run_serving, "ct6": run_ct6, "surrogate": run_surrogate, "fg2d": run_fg2d,
-               "paper": run_paper_tables}[args.only]
+        run = {"serving": lambda t, p: run_serving(t, p, args.serving_batches), "ct6": run_ct6,
+               "surrogate": run_surrogate, "fg2d": run_fg2d, "paper": run_paper_tables}[args.only]
         print(json.dumps({args.only: run(torch, Plan)}), flush=True)
         return
     w = I.workload_ct4()
@@ -593,7 +596,7 @@ def main():
     if not args.no_fg2d:
         res["fg2d_65x65"] = run_fg2d(torch, Plan)
     if not args.no_serving:
-        res["serving_batch4"] = run_serving(torch, Plan)
+        res["serving_batch4"] = run_serving(torch, Plan, args.serving_batches)
     if not args.no_ct6:
         res["ct6_fp32_richardson"] = run_ct6(torch, Plan)
     if not args.no_surrogate:
