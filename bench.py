@@ -466,15 +466,15 @@ def cpu_baseline(w, target_seconds=12.0):
     units = np.empty(len(sel))
     out = np.zeros(1)
 
-    def run(steps):
+    def run(steps, ngrids=len(sel), nthreads=threads):
         # orc_price_grids solves to the problem's maturity with `steps` steps: scale the maturity
         # so that dt stays the workload's T / steps
         ps = oracle.problem_struct(p)
         ps.T = p.T * steps / w["steps"]
         t0 = time.perf_counter()
         rc = L.orc_price_grids(C.byref(ps), lvc.ctypes.data_as(C.POINTER(C.c_int32)),
-                               coef.ctypes.data_as(C.POINTER(C.c_double)), len(sel), C.byref(sc), steps,
-                               threads, units.ctypes.data_as(C.POINTER(C.c_double)),
+                               coef.ctypes.data_as(C.POINTER(C.c_double)), ngrids, C.byref(sc), steps,
+                               nthreads, units.ctypes.data_as(C.POINTER(C.c_double)),
                                out.ctypes.data_as(C.POINTER(C.c_double)))
         assert rc == 0
         return time.perf_counter() - t0
@@ -483,12 +483,21 @@ def cpu_baseline(w, target_seconds=12.0):
     steps = int(min(w["steps"], max(6, round(6 * target_seconds / max(t6, 1e-3)))))
     dt = run(steps)
     su = float(sum(1 << int(s) for s in sel.sum(axis=1))) * 2 * steps
+    # the same grids on one thread: 2 grids, steps sized to about a quarter of the target
+    g1 = min(2, len(sel))
+    t1 = run(2, g1, 1)
+    steps1 = int(min(w["steps"], max(2, round(2 * target_seconds / 4 / max(t1, 1e-3)))))
+    dt1 = run(steps1, g1, 1)
+    su1 = float(g1 * (1 << int(sums.min()))) * 2 * steps1
     return {"value": su / dt, "unit": "stage-updates/s", "cores": threads, "kind": "oracle",
             "seconds": dt,
             "sample": "%d of %d component grids (smallest layer, %d inner points each), %d of %d time "
                       "steps at the workload's dt, FP64 CPU oracle" % (len(sel), len(lv),
                                                                       1 << int(sums.min()), steps,
                                                                       w["steps"]),
+            "single_thread": {"value": su1 / dt1, "unit": "stage-updates/s", "cores": 1,
+                              "seconds": dt1,
+                              "sample": "%d grids of the same layer, %d time steps" % (g1, steps1)},
             "cpu_model": _cpu_model()}
 
 

@@ -19,7 +19,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "amfrw_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# AMF_ORACLE_LIB names another build of the same source (the sanitizer test loads one built with
+# ASan/UBSan); by default the library beside this file is used and built on first use.
+_LIB = os.environ.get("AMF_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 MAXD = 8
 MAXS = 6
 

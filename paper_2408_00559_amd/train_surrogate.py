@@ -6,6 +6,9 @@ what it gains over the solver on held-out requests.
                                                          [--max-seconds S]
     # training, calibration and evaluation from the stored labels
     python -m paper_2408_00559_amd.train_surrogate train --dir D --out O
+    # discretisation error of the labels: the same held-out requests at levels n .. n+3 and at
+    # twice the steps on the finest level
+    python -m paper_2408_00559_amd.train_surrogate label-accuracy --dir D --out O [--count 128]
 
 Labels: d = 6 (5 rates + V) modified combination technique (psi = 1, level --n), --steps AMFR-W2
 steps, FP32 solver (autotuned schedule) with FP64 combination, instances drawn by
@@ -144,9 +147,41 @@ def train(a, log):
     return 0
 
 
+def label_accuracy(a, log):
+    """Prices of `count` held-out requests (seed 6) at levels n .. n+3 of the same combination and
+    steps, and at the finest level with twice the steps; the label level's difference from the
+    finest is its discretisation error as far as these levels resolve it.  Plans hold 32 requests
+    (under 1e9 inner points at level n + 3 = 8)."""
+    os.makedirs(a.out, exist_ok=True)
+    probs = I.surrogate_instances(a.count, 6)
+    runs = [(n, a.steps) for n in range(a.n, a.n + 4)] + [(a.n + 3, 2 * a.steps)]
+    prices = {}
+    for n, steps in runs:
+        t0 = time.perf_counter()
+        prices[(n, steps)] = np.asarray(S.solver_prices(probs, I.combination(n, a.psi), steps,
+                                                        chunk=32, tune=False), dtype=np.float64)
+        log("level %d, %d steps: %.1f s" % (n, steps, time.perf_counter() - t0))
+    ref = prices[(a.n + 3, 2 * a.steps)]
+    scale = np.abs(ref)
+    rep = {"d": 6, "psi": a.psi, "requests": a.count, "seed": 6, "precision": "fp32 (FP64 combine)",
+           "reference": {"n": a.n + 3, "steps": 2 * a.steps}, "levels": []}
+    for (n, steps), v in prices.items():
+        rel = np.abs(v - ref) / scale
+        rep["levels"].append({"n": n, "steps": steps, "non_positive": int(np.sum(v <= 0)),
+                              "rel_diff_median": float(np.median(rel)),
+                              "rel_diff_p90": float(np.quantile(rel, 0.9)),
+                              "rel_diff_max": float(np.max(rel)),
+                              "abs_diff_median": float(np.median(np.abs(v - ref)))})
+    rep["reference_non_positive"] = int(np.sum(ref <= 0))
+    rep["reference_price_median"] = float(np.median(ref))
+    json.dump(rep, open(os.path.join(a.out, "label_accuracy.json"), "w"), indent=1)
+    log(json.dumps(rep))
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("mode", choices=["labels", "train"])
+    ap.add_argument("mode", choices=["labels", "train", "label-accuracy"])
     ap.add_argument("--dir", required=True, help="label directory")
     ap.add_argument("--out", default=None)
     ap.add_argument("--train", type=int, default=200000)
@@ -161,12 +196,15 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--serve-sample", type=int, default=4096)
+    ap.add_argument("--count", type=int, default=128, help="requests of the label-accuracy study")
     a = ap.parse_args(argv)
     log = lambda m: print(m, flush=True)
     if a.mode == "labels":
         return labels(a, log)
     if not a.out:
-        ap.error("train needs --out")
+        ap.error("%s needs --out" % a.mode)
+    if a.mode == "label-accuracy":
+        return label_accuracy(a, log)
     return train(a, log)
 
 

@@ -59,10 +59,19 @@ def test_gradients_match_reference():
     p = net.params().cpu().numpy().astype(np.float64)
     y, cache = M.forward(lay, p, x, mean, std, bf16=True)
     gr = M.backward(lay, cache, dy, bf16=True)
+    # Both sides round the same activations to BF16 (8 significant bits), but from sums taken in a
+    # different order (FP32 MFMA vs FP64), so an activation whose value lies near a rounding boundary
+    # can round one BF16 ulp (2^-8) apart and move the gradient entries it feeds by that much.  Such
+    # flips are isolated: the gradient of each parameter block agrees to 1e-2 in the 2-norm, and no
+    # single entry is further off than 3e-2 of the block's largest entry.
     for l in range(lay.layers):
         for off, size in ((lay.w_off[l], lay.rows[l] * lay.cols[l]), (lay.b_off[l], lay.rows[l])):
             a, b = g[off:off + size], gr[off:off + size]
             scale = np.max(np.abs(b)) + 1e-30
+            norm_rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
+            print("layer %d block of %d: max %.2e, 2-norm %.2e" % (l, size, np.max(np.abs(a - b)) / scale,
+                                                                 norm_rel))
+            assert norm_rel < 1e-2, (l, norm_rel)
             assert np.max(np.abs(a - b)) < 3e-2 * scale, (l, np.max(np.abs(a - b)) / scale)
 
 
