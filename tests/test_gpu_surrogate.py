@@ -61,9 +61,9 @@ def test_gradients_match_reference():
     gr = M.backward(lay, cache, dy, bf16=True)
     # Both sides round the same activations to BF16 (8 significant bits), but from sums taken in a
     # different order (FP32 MFMA vs FP64), so an activation whose value lies near a rounding boundary
-    # can round one BF16 ulp (2^-8) apart and move the gradient entries it feeds by that much.  Such
-    # flips are isolated: the gradient of each parameter block agrees to 1e-2 in the 2-norm, and no
-    # single entry is further off than 3e-2 of the block's largest entry.
+    # can round one BF16 ulp (2^-8) apart and move the gradient entries it feeds.  Such flips are
+    # rare and isolated: on these inputs the blocks agree to better than 1e-4 in the 2-norm and
+    # 2e-4 of the largest entry; the bounds below leave a factor of about ten.
     for l in range(lay.layers):
         for off, size in ((lay.w_off[l], lay.rows[l] * lay.cols[l]), (lay.b_off[l], lay.rows[l])):
             a, b = g[off:off + size], gr[off:off + size]
@@ -71,8 +71,8 @@ def test_gradients_match_reference():
             norm_rel = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
             print("layer %d block of %d: max %.2e, 2-norm %.2e" % (l, size, np.max(np.abs(a - b)) / scale,
                                                                  norm_rel))
-            assert norm_rel < 1e-2, (l, norm_rel)
-            assert np.max(np.abs(a - b)) < 3e-2 * scale, (l, np.max(np.abs(a - b)) / scale)
+            assert norm_rel < 1e-3, (l, norm_rel)
+            assert np.max(np.abs(a - b)) < 2e-3 * scale, (l, np.max(np.abs(a - b)) / scale)
 
 
 def test_training_reduces_loss():
