@@ -579,13 +579,15 @@ struct GpuMem {
     __device__ __forceinline__ void sw(int i, T v) const { lds[i] = v; }
 };
 
-// One block.  Per step: plane j_V + 2 (loaded during the previous step) into its slot, plane j_V + 3
-// and the next node's stage values loaded, plane j_V computed and stored.  Loads are issued in the
-// order they are waited for, so no wait covers a load issued later in the same step.
+// One block.  Per step: plane j_V + 2 (loaded MARCH_DEPTH steps before) into its slot, plane
+// j_V + 2 + MARCH_DEPTH and the next node's stage values loaded, plane j_V computed and stored.  Loads
+// are issued in the order they are waited for, so no wait covers a load issued later in the same
+// step, and each plane's loads have MARCH_DEPTH steps to arrive.
 template <typename T, int D, int OP, class Sh>
 __device__ __forceinline__ void march_block(const DevPlan& P, const StencilArgs& A, const MarchBlk& B, T* smem)
 {
     constexpr int NPF = Sh::NPF;
+    constexpr int DP = MARCH_DEPTH;
     GpuMem<T> m{smem};
     const UnitDev& U = P.units[B.unit];
     MarchGeo<D> G;
@@ -612,46 +614,73 @@ __device__ __forceinline__ void march_block(const DevPlan& P, const StencilArgs&
     T* W = (T*)A.W;
     const bool act = t.active;
     // the values the stage combination needs at this thread's node of plane jv
-    auto centre = [&](int jv, T& e0, T& e1, bool live) {
+    auto centre = [&](int jv, T (&e)[2], bool live) {
         const int64_t b = march_plane_base<D>(G, jv), n = live ? march_plane_len<D>(G, jv) : 0;
-        e0 = m.pld(m.plane(cE, b, n), t.gob);                 // K^(0) for the refinement
-        e1 = OP == OP_STAGE2 ? m.pld(m.plane(X2, b, n), t.gob) : T(0);
+        e[0] = m.pld(m.plane(cE, b, n), t.gob);               // K^(0) for the refinement
+        e[1] = OP == OP_STAGE2 ? m.pld(m.plane(X2, b, n), t.gob) : T(0);
     };
     march_vsq<T, D, Sh>(G, tid, tV, m);
-    // planes v0 .. v0 + 2 into their slots (plane 0 is the lower face: zeros), plane v0 + 3 in flight
-    for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
-        march_fetch<T, D, OP>(G, p, X0, X1, av, t, m);
-        march_stash<T, D, Sh>(G, tid, p, t, m);
+    // planes v0 .. v0 + 2 into their slots (plane 0 is the lower face: zeros), planes v0 + 3 ..
+    // v0 + 2 + DP in flight: plane v0 + i goes to register set i mod DP, and the set is stashed
+    // before it is loaded again
+    MarchPf<T, OP, NPF> pf[DP];
+#pragma unroll
+    for (int i = 0; i < 3 + DP; ++i) {
+        const int p = G.v0 + i;
+        if (i >= DP && p - DP <= last) march_stash<T, D, Sh>(G, tid, p - DP, pf[(i - DP) % DP], av, m);
+        march_fetch<T, D, OP>(G, p, X0, X1, t, pf[i % DP], m, p <= last);
     }
-    if (G.v0 + 3 <= last) march_fetch<T, D, OP>(G, G.v0 + 3, X0, X1, av, t, m);
-    T ea0, ea1, eb0 = T(0), eb1 = T(0);
-    centre(G.v0 + 1, ea0, ea1, true);
+    T ce[2][2] = {};
+    centre(G.v0 + 1, ce[0], true);
     __syncthreads();
-    // step s computes plane v0 + s from the stage values in (c0_, c1_) and loads those of the next
-    // plane into (n0_, n1_); the two register pairs alternate, so no value is copied between steps
-    // (a copy would wait for the load just issued).  Every step issues the same loads (empty ranges
-    // past the block's planes), so each wait covers exactly the loads of the step before.
-    auto step = [&](int s, T c0_, T c1_, T& n0_, T& n1_) {
+    // crosses of the planes v0 and v0 + 1 (stashed above); each step reads that of plane jv + 1
+    constexpr int NX = MarchX<D>::N;
+    T xw[3][NX];
+    if (act) {
+        march_cross<T, D, Sh>(G, t, G.v0, xw[0], m);
+        march_cross<T, D, Sh>(G, t, G.v0 + 1, xw[1], m);
+    }
+    // step s = position k in a period of 6 computes plane v0 + s from the crosses of planes jv - 1
+    // and jv (register sets k and k + 1 mod 3) and jv + 1 (read into set k + 2 mod 3) and from the
+    // stage values in set k mod 2, and loads those of the next plane into the other set.  The
+    // register sets rotate, so no value is copied between steps (a copy of a loaded value would wait
+    // for its load).  Every step issues the same global loads (empty ranges past the block's planes),
+    // so each wait covers exactly the loads of the steps before.
+    auto step = [&](auto K, int s) {
+        constexpr int k = decltype(K)::value;
         const int jv = G.v0 + s;
-        // plane jv + 2 goes into the slot of plane jv - 2, which the previous step read
-        if (jv + 2 <= last) march_stash<T, D, Sh>(G, tid, jv + 2, t, m);
-        march_fetch<T, D, OP>(G, jv + 3, X0, X1, av, t, m, jv + 3 <= last);
-        centre(jv + 1, n0_, n1_, s < G.vn);
+        MarchPf<T, OP, NPF>& q = pf[(k + 1) % DP];          // holds plane jv + 2
+        // plane jv + 2 goes into the slot of plane jv - 2, which no thread has read since the
+        // barrier before the previous step
+        if (jv + 2 <= last) march_stash<T, D, Sh>(G, tid, jv + 2, q, av, m);
+        march_fetch<T, D, OP>(G, jv + 2 + DP, X0, X1, t, q, m, jv + 2 + DP <= last);
+        centre(jv + 1, ce[(k + 1) % 2], s < G.vn);
         const T vsq = march_vsq_of<T, D, Sh>(G, s, m);
         if (act) {
-            T c0;
-            const T F = march_F<T, D, Sh>(G, t, jv, vsq, tdV, c0, m);
+            if (jv < MV) march_cross<T, D, Sh>(G, t, jv + 1, xw[(k + 2) % 3], m);   // uniform over the block
+            const T F = march_F<T, D, Sh>(G, t, jv, vsq, tdV, xw[k % 3], xw[(k + 1) % 3], xw[(k + 2) % 3], m);
+            const T c0_ = ce[k % 2][0], c1_ = ce[k % 2][1];
             T o;
             if constexpr (OP == OP_STAGE1) o = sc * (F + c0_);
             else if constexpr (OP == OP_STAGE2) o = sc * (F + c0_) + qv * c1_;
-            else o = T(2) * c0_ - c0 + sc * F;
+            else o = T(2) * c0_ - xw[(k + 1) % 3][0] + sc * F;
             m.pst(m.plane(W, march_plane_base<D>(G, jv), march_plane_len<D>(G, jv)), t.gob, o);
         }
         __syncthreads();
     };
-    for (int s = 1; s <= G.vn; s += 2) {
-        step(s, ea0, ea1, eb0, eb1);
-        if (s + 1 <= G.vn) step(s + 1, eb0, eb1, ea0, ea1);
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using I4 = std::integral_constant<int, 4>;
+    using I5 = std::integral_constant<int, 5>;
+    for (int s = 1; s <= G.vn; s += 6) {
+        step(I0{}, s);
+        if (s + 1 <= G.vn) step(I1{}, s + 1);
+        if (s + 2 <= G.vn) step(I2{}, s + 2);
+        if (s + 3 <= G.vn) step(I3{}, s + 3);
+        if (s + 4 <= G.vn) step(I4{}, s + 4);
+        if (s + 5 <= G.vn) step(I5{}, s + 5);
     }
 }
 

@@ -7,11 +7,12 @@
 // A block owns one tile of the plane axes 0..d-2 of one unit (T_0 x T_1 x T_2 nodes, one node per
 // thread) and walks the V axis (axis d-1) over a range of planes.  The values it needs from the
 // planes j_V - 1, j_V, j_V + 1 (the tile plus a one-node halo on every plane axis) sit in a ring of
-// four LDS plane slots: while the nodes of plane j_V are computed from three slots, the plane
-// j_V + 2 (loaded into registers during the previous step) is written into the fourth slot, which no
-// thread reads in that step, and plane j_V + 3 is loaded; one barrier per plane suffices and two
-// planes are in flight.  Every neighbour read of the 19-row stencil then
-// comes from LDS; the unit is read from global memory once plus the tile halos.
+// four LDS plane slots: while the nodes of plane j_V are computed, the plane j_V + 2 (loaded into
+// registers during the previous step) is written into the slot of plane j_V - 2, which no thread
+// reads in that step, and plane j_V + 3 is loaded; one barrier per plane suffices and two planes are
+// in flight.  Every neighbour of the 19-row stencil comes from LDS or, for the node's own column on
+// the planes j_V - 1 and j_V, from registers that carry it between steps (march_cross); the unit is
+// read from global memory once plus the tile halos.
 //
 // A halo element beyond a lower face holds 0 (the lower faces are zero in the state W = Y - g); one
 // beyond an upper face holds the node below that face, the Neumann ghost u_{M+1} = u_{M-1} of
@@ -34,11 +35,13 @@
 
 #include "amfrw_consts.h"
 
+
 namespace amf {
 
 constexpr int MARCH_THREADS = 256;      // threads per block = nodes per tile plane (at most)
 constexpr int MARCH_SEG = 32;           // V planes per block
 constexpr int MARCH_SLOTS = 4;          // LDS ring of plane slots
+constexpr int MARCH_DEPTH = 1;          // planes whose loads are in flight during a step (1 or 2)
 constexpr int MARCH_MAX_PLANE = 1280;   // elements per plane slot (tile plus halo)
 constexpr int MARCH_PF = MARCH_MAX_PLANE / MARCH_THREADS;   // prefetch registers per thread (at most)
 constexpr uint32_t MARCH_NONE = 0x7FFFFFF0u;  // byte offset of a zero element: beyond every plane
@@ -272,7 +275,7 @@ __host__ __device__ __forceinline__ void march_dispatch(int shape, F&& f)
 
 // Per-thread state kept across phases: its node in the tile, the coefficient products of its node
 // on the plane axes (fixed while the thread walks V), the byte offsets (inside one V plane) of the
-// slot elements it fetches, and the prefetch registers.
+// slot elements it fetches.
 template <typename T, int D, int NPF>
 struct MarchThr {
     int x[3];            // position in the tile
@@ -286,7 +289,6 @@ struct MarchThr {
     T cpair[3];          // rho_ik tmix_i tmix_k for the plane-axis pairs (0,1), (0,2), (1,2); 0 on a face
     T cv[3];             // sigma phi_i tmix_i tmix_V for the pairs (i, V); 0 on a face
     uint32_t pfb[NPF];   // byte offsets in a V plane of the fetched slot elements (MARCH_NONE: zero)
-    T pf[NPF];
 };
 
 __host__ __device__ __forceinline__ int march_pair(int i, int k) { return i + k - 1; }   // (0,1)->0 (0,2)->1 (1,2)->2
@@ -395,22 +397,31 @@ __host__ __device__ __forceinline__ int64_t march_plane_len(const MarchGeo<D>& G
     return jv >= 1 && jv <= G.M[D - 1] ? G.E[D - 1] : 0;
 }
 
-// Global -> registers: this thread's share of the slot of plane jv.  OP_STAGE2 stages X0 + a X1.
-// With live = false the loads are still issued but read nothing (a zero-length range): the loop
-// then issues the same loads on every step, which keeps the wait counts exact.
+// Prefetch registers of one plane: this thread's share of the slot, as loaded (x0 from X0 and, for
+// OP_STAGE2, x1 from X1; the stage combination X0 + a X1 is formed when the values go to LDS, so no
+// instruction between the load and the stash waits for the load).
+template <typename T, int OP, int NPF>
+struct MarchPf {
+    T x0[NPF];
+    T x1[OP == OP_STAGE2 ? NPF : 1];
+};
+
+// Global -> registers: this thread's share of the slot of plane jv.  With live = false the loads are
+// still issued but read nothing (a zero-length range): the loop then issues the same loads on every
+// step, which keeps the wait counts exact.
 template <typename T, int D, int OP, int NPF, class Mem>
-__host__ __device__ __forceinline__ void march_fetch(const MarchGeo<D>& G, int jv, const T* X0, const T* X1, T a,
-                                                     MarchThr<T, D, NPF>& t, Mem& m, bool live = true)
+__host__ __device__ __forceinline__ void march_fetch(const MarchGeo<D>& G, int jv, const T* X0, const T* X1,
+                                                     const MarchThr<T, D, NPF>& t, MarchPf<T, OP, NPF>& pf, Mem& m,
+                                                     bool live = true)
 {
     const int64_t b = march_plane_base<D>(G, jv), n = live ? march_plane_len<D>(G, jv) : 0;
     const auto h0 = m.plane(X0, b, n);
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) pf.x0[r] = m.pld(h0, t.pfb[r]);
     if constexpr (OP == OP_STAGE2) {
         const auto h1 = m.plane(X1, b, n);
 #pragma unroll
-        for (int r = 0; r < NPF; ++r) t.pf[r] = m.pld(h0, t.pfb[r]) + a * m.pld(h1, t.pfb[r]);
-    } else {
-#pragma unroll
-        for (int r = 0; r < NPF; ++r) t.pf[r] = m.pld(h0, t.pfb[r]);
+        for (int r = 0; r < NPF; ++r) pf.x1[r] = m.pld(h1, t.pfb[r]);
     }
 }
 
@@ -429,45 +440,71 @@ __host__ __device__ __forceinline__ T march_vsq_of(const MarchGeo<D>& G, int s, 
     return m.sr(MARCH_SLOTS * Sh::lp(G) + s - 1);
 }
 
-// Registers -> the LDS slot of plane jv.
-template <typename T, int D, class Sh, int NPF, class Mem>
+// Registers -> the LDS slot of plane jv (OP_STAGE2: X0 + a X1).
+template <typename T, int D, class Sh, int OP, int NPF, class Mem>
 __host__ __device__ __forceinline__ void march_stash(const MarchGeo<D>& G, int tid, int jv,
-                                                     const MarchThr<T, D, NPF>& t, Mem& m)
+                                                     const MarchPf<T, OP, NPF>& pf, T a, Mem& m)
 {
     const int LP = Sh::lp(G);
     const int base = (jv & (MARCH_SLOTS - 1)) * LP;
 #pragma unroll
     for (int r = 0; r < NPF; ++r) {
         const int e = tid + r * MARCH_THREADS;
-        if (e < LP) m.sw(base + e, t.pf[r]);
+        if (e < LP) {
+            if constexpr (OP == OP_STAGE2) m.sw(base + e, pf.x0[r] + a * pf.x1[r]);
+            else m.sw(base + e, pf.x0[r]);
+        }
     }
 }
 
-// Sketch 1 with zero lower faces at this thread's node of plane jv, from the LDS slots of planes
-// jv - 1, jv, jv + 1: second differences (the upper-face ghosts are stored in the halo), mixed
+// The "cross" of this thread's node on plane jv: the node and its two neighbours along each plane
+// axis, x[0] = centre, x[1 + 2i] = node - e_i, x[2 + 2i] = node + e_i.  A thread keeps the crosses
+// of planes jv - 1 and jv in registers while it walks V, so each step reads only the cross of plane
+// jv + 1 and the in-plane diagonal neighbours of plane jv from LDS (19 values for d = 4, not 33).
+template <int D>
+struct MarchX {
+    static constexpr int N = 2 * D - 1;
+};
+
+template <typename T, int D, class Sh, int NPF, class Mem>
+__host__ __device__ __forceinline__ void march_cross(const MarchGeo<D>& G, const MarchThr<T, D, NPF>& t, int jv,
+                                                     T (&x)[MarchX<D>::N], Mem& m)
+{
+    const int S[3] = {1, Sh::s1(G), Sh::s2(G)};
+    const int sc = (jv & (MARCH_SLOTS - 1)) * Sh::lp(G) + t.c;
+    x[0] = m.sr(sc);
+#pragma unroll
+    for (int i = 0; i < D - 1; ++i) {
+        x[1 + 2 * i] = m.sr(sc - S[i]);
+        x[2 + 2 * i] = m.sr(sc + S[i]);
+    }
+}
+
+// Sketch 1 with zero lower faces at this thread's node of plane jv, from the crosses of planes
+// jv - 1, jv, jv + 1 (xm, xc, xp; xp is not read on the V face) and the diagonal neighbours of the
+// LDS slot of plane jv: second differences (the upper-face ghosts are stored in the halo), mixed
 // differences for every pair (zero on either upper face: folded into cpair and cv), advection on the
 // plane axes 1..d-2 (zero on the upper face: folded into adv).  Returns F before the stage
 // combination (vsq = V^2 of the plane, tdV = sigma^2 / (2 h_V^2)); 0 on a Dirichlet rate face.
-// c0 receives the node's own value.  The only branch is on the V face, uniform over the block.
+// The only branch is on the V face, uniform over the block.
 template <typename T, int D, class Sh, int NPF, class Mem>
 __host__ __device__ __forceinline__ T march_F(const MarchGeo<D>& G, const MarchThr<T, D, NPF>& t, int jv, T vsq,
-                                              T tdV, T& c0, Mem& m)
+                                              T tdV, const T (&xm)[MarchX<D>::N], const T (&xc)[MarchX<D>::N],
+                                              const T (&xp)[MarchX<D>::N], Mem& m)
 {
-    const int LP = Sh::lp(G);
     const int S[3] = {1, Sh::s1(G), Sh::s2(G)};
-    const int sm = ((jv - 1) & (MARCH_SLOTS - 1)) * LP + t.c, sc = (jv & (MARCH_SLOTS - 1)) * LP + t.c,
-              sp = ((jv + 1) & (MARCH_SLOTS - 1)) * LP + t.c;
-    c0 = m.sr(sc);
+    const int sc = (jv & (MARCH_SLOTS - 1)) * Sh::lp(G) + t.c;
+    const T c0 = xc[0];
     const bool vtop = jv == G.M[D - 1];                      // uniform over the block
-    const T vm = m.sr(sm);
-    const T vp = vtop ? vm : m.sr(sp);
+    const T vm = xm[0];
+    const T vp = vtop ? vm : xp[0];
     T acc = tdV * (vp - T(2) * c0 + vm);
 #pragma unroll
     for (int i = 0; i < D - 1; ++i) {
-        const T xm = m.sr(sc - S[i]);
-        const T xp = m.sr(sc + S[i]);
-        acc += t.tdiff[i] * (xp - T(2) * c0 + xm);
-        if (i > 0) acc += t.adv[i] * (xp - xm);             // no advection term on axis 0
+        const T lo = xc[1 + 2 * i];
+        const T hi = xc[2 + 2 * i];
+        acc += t.tdiff[i] * (hi - T(2) * c0 + lo);
+        if (i > 0) acc += t.adv[i] * (hi - lo);             // no advection term on axis 0
 #pragma unroll
         for (int k = i + 1; k < D - 1; ++k) {
             const T xx = m.sr(sc + S[i] + S[k]) + m.sr(sc - S[i] - S[k]) - m.sr(sc + S[i] - S[k]) -
@@ -478,7 +515,7 @@ __host__ __device__ __forceinline__ T march_F(const MarchGeo<D>& G, const MarchT
     if (!vtop) {
 #pragma unroll
         for (int i = 0; i < D - 1; ++i) {
-            const T xx = m.sr(sp + S[i]) + m.sr(sm - S[i]) - m.sr(sm + S[i]) - m.sr(sp - S[i]);
+            const T xx = xp[2 + 2 * i] + xm[1 + 2 * i] - xm[2 + 2 * i] - xp[1 + 2 * i];
             acc += t.cv[i] * xx;
         }
     }

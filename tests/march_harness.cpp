@@ -8,6 +8,8 @@
 //     barrier in between,
 // and it counts the writes of every node: each inner node of each unit must be written exactly once.
 // Built by tests/test_march_harness.py with g++ and loaded through ctypes.
+#include <array>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -142,9 +144,11 @@ struct CheckedMem {
 };
 
 // One block in the kernel's order: V^2 factors into LDS, planes v0 .. v0 + 2 fetched and stashed,
-// plane v0 + 3 fetched, the first node's stage values loaded, barrier; per step stash plane jv + 2,
-// fetch plane jv + 3 (an empty range past the block's last plane), load the next node's stage values
-// (an empty range on the last step), compute and store plane jv, barrier.
+// planes v0 + 3 .. v0 + 2 + MARCH_DEPTH fetched (register set i mod MARCH_DEPTH for plane v0 + i), the
+// first node's stage values loaded, barrier, the crosses of planes v0 and v0 + 1 read; per step stash
+// plane jv + 2, fetch plane jv + 2 + MARCH_DEPTH into the same registers (an empty range past the
+// block's last plane), load the next node's stage values (an empty range on the last step), read the
+// cross of plane jv + 1 (not on the V face), compute and store plane jv, barrier.
 template <int D, int OP, class Sh>
 void walk_block(const MarchBlk& B, const int8_t* ul, int64_t uoff, int64_t total, CheckedMem& m, std::vector<double>& X0,
                 std::vector<double>& X1, std::vector<double>& cG, std::vector<double>& X2, std::vector<double>& W,
@@ -217,29 +221,57 @@ void walk_block(const MarchBlk& B, const int8_t* ul, int64_t uoff, int64_t total
     };
     const double* tV = tab + utab[D - 1];
     std::vector<std::pair<double, double>> cur((size_t)MARCH_THREADS), nxt((size_t)MARCH_THREADS);
+    constexpr int DP = MARCH_DEPTH;
+    std::vector<std::array<MarchPf<double, OP, NPF>, DP>> pf((size_t)MARCH_THREADS);
     for (int t = 0; t < MARCH_THREADS; ++t) {
         m.tid = t;
         march_vsq<double, D, Sh>(G, t, tV, m);
-        for (int p = G.v0; p <= G.v0 + 2 && p <= last; ++p) {
-            march_fetch<double, D, OP>(G, p, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
-            march_stash<double, D, Sh>(G, t, p, thr[(size_t)t], m);
+        for (int i = 0; i < 3 + DP; ++i) {
+            const int p = G.v0 + i;
+            if (i >= DP && p - DP <= last)
+                march_stash<double, D, Sh>(G, t, p - DP, pf[(size_t)t][(size_t)((i - DP) % DP)], 0.5, m);
+            march_fetch<double, D, OP>(G, p, X0.data(), X1.data(), thr[(size_t)t], pf[(size_t)t][(size_t)(i % DP)], m,
+                                       p <= last);
         }
-        if (G.v0 + 3 <= last) march_fetch<double, D, OP>(G, G.v0 + 3, X0.data(), X1.data(), 0.5, thr[(size_t)t], m);
         cur[(size_t)t] = centre(t, G.v0 + 1, true);
     }
     ++m.epoch;                                               // __syncthreads
+    // crosses of planes v0 and v0 + 1, then each step the cross of plane jv + 1 (register window)
+    constexpr int NX = MarchX<D>::N;
+    std::vector<std::array<std::array<double, NX>, 3>> win((size_t)MARCH_THREADS);
+    auto cross = [&](int t, int jv, int slot) {
+        double x[NX];
+        march_cross<double, D, Sh>(G, thr[(size_t)t], jv, x, m);
+        for (int k = 0; k < NX; ++k) win[(size_t)t][(size_t)slot][(size_t)k] = x[k];
+    };
+    for (int t = 0; t < MARCH_THREADS; ++t) {
+        m.tid = t;
+        if (!thr[(size_t)t].active) continue;
+        cross(t, G.v0, 0);
+        cross(t, G.v0 + 1, 1);
+    }
     for (int s = 1; s <= G.vn && !err.set; ++s) {
         const int jv = G.v0 + s;
+        const int im = (s - 1) % 3, ic = s % 3, ip = (s + 1) % 3;
         for (int t = 0; t < MARCH_THREADS; ++t) {
             m.tid = t;
             MarchThr<double, D, NPF>& th = thr[(size_t)t];
-            if (jv + 2 <= last) march_stash<double, D, Sh>(G, t, jv + 2, th, m);
-            march_fetch<double, D, OP>(G, jv + 3, X0.data(), X1.data(), 0.5, th, m, jv + 3 <= last);
+            MarchPf<double, OP, NPF>& q = pf[(size_t)t][(size_t)(((s - 1) + 1) % DP)];   // holds plane jv + 2
+            if (jv + 2 <= last) march_stash<double, D, Sh>(G, t, jv + 2, q, 0.5, m);
+            march_fetch<double, D, OP>(G, jv + 2 + DP, X0.data(), X1.data(), th, q, m, jv + 2 + DP <= last);
             nxt[(size_t)t] = centre(t, jv + 1, s < G.vn);
             const double vsq = march_vsq_of<double, D, Sh>(G, s, m);
             if (th.active) {
-                double c0;
-                const double F = march_F<double, D, Sh>(G, th, jv, vsq, m.tab(tV, MV), c0, m);
+                if (jv < MV) cross(t, jv + 1, ip);
+                double xm[NX], xc[NX], xp[NX];
+                for (int k = 0; k < NX; ++k) {
+                    xm[k] = win[(size_t)t][(size_t)im][(size_t)k];
+                    xc[k] = win[(size_t)t][(size_t)ic][(size_t)k];
+                    xp[k] = jv < MV ? win[(size_t)t][(size_t)ip][(size_t)k] : std::nan("");
+                }
+                const double F = march_F<double, D, Sh>(G, th, jv, vsq, m.tab(tV, MV), xm, xc, xp, m);
+                if (F != F) err("the operator used the cross of the plane beyond the V face");
+                const double c0 = xc[0];
                 const double e0 = cur[(size_t)t].first, e1 = cur[(size_t)t].second;
                 double o;
                 if (OP == OP_STAGE1) o = 0.1 * (F + e0);
