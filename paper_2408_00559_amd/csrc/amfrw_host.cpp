@@ -64,7 +64,7 @@ struct amf_plan {
     int stencil_r = 1, min_m0 = 1, max_m0 = 1, xcd = 1;
     int fuse0 = 0;                         // fused axis-0 solve in the operator launches
     bool res_ok = false;                   // every unit fits the unit-resident schedule
-    int resident = 0, res_lds_len = 0;
+    int resident = 0, res_lds_len = 0, res_tab_len = 0;
     std::vector<int32_t> ax_units[MAXD];
     std::vector<int64_t> ax_line_off[MAXD];
     std::vector<SweepBlk> ax_blk[MAXD];
@@ -603,7 +603,18 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
         for (int u = 0; u < P->n_units; ++u) max_lsum = std::max(max_lsum, (int)P->units[u].lsum);
         P->res_ok = max_lsum <= (precision == AMF_FP64 ? RES_MAX_LSUM_F64 : RES_MAX_LSUM_F32) &&
                     scheme->stages == 2 && scheme->w_matrix == AMF_W_AMF;
-        P->res_lds_len = (1 << max_lsum) + ((1 << max_lsum) >> 4);
+        // unit-resident LDS: four vectors of axis-1 rows at pitch res_pitch(M_1), then the unit's
+        // 1-D coefficient tables (3 M_i per rate axis, M_V + 2 for V)
+        P->res_lds_len = 0;
+        P->res_tab_len = 0;
+        for (int u = 0; u < P->n_units; ++u) {
+            const UnitDev& U = P->units[u];
+            const int m0 = 1 << U.lv[0];
+            P->res_lds_len = std::max(P->res_lds_len, ((1 << U.lsum) / m0) * res_pitch(m0));
+            int tl = 0;
+            for (int i = 0; i < d; ++i) tl += i < d - 1 ? 3 * (1 << U.lv[i]) : (1 << U.lv[i]) + 2;
+            P->res_tab_len = std::max(P->res_tab_len, tl);
+        }
         const int rmax = precision == AMF_FP64 ? STENCIL_R_F64 : STENCIL_R_F32;
         P->stencil_r = rmax;                   // each unit runs at min(stencil_r, M_1)
         // per axis (one host thread each): units ordered by M_axis, line offsets, blocks that
@@ -1067,6 +1078,7 @@ amf_status advance(amf_plan* P, int run, int n, hipStream_t s)
         a.b1 = P->sch.b[0];
         a.b2 = P->sch.b[1];
         a.lds_len = P->res_lds_len;
+        a.tab_len = P->res_tab_len;
         hipError_t e = timed(P, AMF_K_RESIDENT, (2.0 + 2.0 * n) * P->vbytes(), s,
                              [&] { return launch_resident(P->dev, P->prec, a, s); });
         return e == hipSuccess ? AMF_OK : hip_fail(e, "resident");

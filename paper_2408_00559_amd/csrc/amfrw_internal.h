@@ -168,15 +168,19 @@ struct SweepArgs {
 
 // Unit-resident schedule: one workgroup of RES_BLOCK threads per unit, the whole time loop in LDS.
 constexpr int RES_BLOCK = 128;
-constexpr int RES_MAX_LSUM_F32 = 11;   // units up to 2048 points (4 padded FP32 vectors: 34.8 KB)
-constexpr int RES_MAX_LSUM_F64 = 10;   // units up to 1024 points (4 padded FP64 vectors: 34.8 KB)
+constexpr int RES_MAX_LSUM_F32 = 11;   // units up to 2048 points (4 FP32 vectors: at most 40 KB)
+constexpr int RES_MAX_LSUM_F64 = 10;   // units up to 1024 points (4 FP64 vectors: at most 40 KB)
+// Pitch of the axis-1 rows of a resident unit in LDS: one padding element per row of 4 or more
+// nodes, so that the lanes of an axis-1 line solve (one row each) fall on distinct banks.
+__host__ __device__ __forceinline__ int res_pitch(int m0) { return m0 >= 4 ? m0 + 1 : m0; }
 
 struct ResArgs {
     void* W;              // solution W (global), read at entry and written at exit
     const void* cG;       // F(g) (global)
     int run, nsteps;
     double a21, q21, b1, b2;
-    int lds_len;          // padded elements per LDS vector (li of the largest unit)
+    int lds_len;          // elements per LDS vector: the largest unit's rows at res_pitch(M_1)
+    int tab_len;          // elements of the largest unit's 1-D coefficient tables
 };
 
 // out = (acc ? out : 0) + sum_{j < n} c_j in_j over every element of a grid vector.

@@ -1294,83 +1294,103 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArg
 
 // ------------------------------------------------------------------------------------------------
 // Unit-resident schedule: one workgroup per unit advances it by n AMFR-W steps with W, K1 and two
-// work vectors in LDS; only W (in and out), F(g) (read per stage) and the tabulated Thomas
-// factors touch global memory.  LDS arrays are padded by one element per 16 (li) so that lanes walking lines of
-// any axis hit distinct banks.
-__device__ __forceinline__ int li(int n) { return n + (n >> 4); }
-
+// work vectors in LDS; W (in and out), F(g) (read per stage) and the tabulated Thomas factors are its
+// only global traffic.  A vector holds the axis-1 rows of M_1 nodes at a pitch P = res_pitch(M_1),
+// so a node's LDS offset is affine in its indices (strides S_1 = 1, S_2 = P, S_k = P M_2 .. M_{k-1})
+// and every neighbour or line element is one add away.  The unit's 1-D coefficient tables follow the
+// four vectors.
 template <int D>
 struct ResGeom {
-    int M[D], S[D];   // extents and index shifts (E_i = 1 << S_i)
-    int Pn, SV, MV;
+    int M[D], L[D];   // extents and their log2
+    int S[D];         // LDS strides of the axes
+    int N[D];         // node-index shifts of the axes (node n = sum_i (j_i - 1) << N_i)
+    int tb[D];        // offset of each axis' coefficient table in the LDS table area
+    int Pn, P0, MV;
 };
 
-// Zero-face Sketch-1 operator on LDS vectors, fused with the stage combination OP.
-template <typename T, int D, int OP>
-__device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const UnitDev& U, const T* tab, const T* cst,
-                                            int dirichlet, T sc, T av, T qv, const T* X0, const T* X1, T* Wout,
-                                            const T* cGg)
+// LDS offset of inner node n (0-based node index of the unit).
+template <int D>
+__device__ __forceinline__ int res_at(const ResGeom<D>& G, int n)
 {
+    return (n & (G.M[0] - 1)) + (n >> G.L[0]) * G.P0;
+}
+
+// Zero-face Sketch-1 operator on LDS vectors, fused with the stage combination OP, one node per
+// thread and iteration.  Lower-face neighbours are 0 and the upper-face ghost is the node below the
+// face (eq. bound1); a neighbour beyond a face is read at the node itself (an index inside the unit)
+// and replaced by a select, and the mixed and advection coefficients vanish on the upper faces.
+template <typename T, int D, int OP>
+__device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const T* st, const T* cst, int dirichlet, T sc,
+                                            T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
+{
+    const T* tv = st + G.tb[D - 1];
+    const T tdV = tv[G.MV], tmixV = tv[G.MV + 1];
     for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) {
-        int j[D];
+        int j[D];                                 // 0-based node indices
+        bool lo[D], hi[D];
+        int dm[D], dp[D];                         // offsets of the lower / upper neighbours (0 beyond a face)
 #pragma unroll
-        for (int i = 0; i < D; ++i) j[i] = ((n >> G.S[i]) & (G.M[i] - 1)) + 1;
+        for (int i = 0; i < D; ++i) {
+            j[i] = (n >> G.N[i]) & (G.M[i] - 1);
+            lo[i] = j[i] == 0;
+            hi[i] = j[i] == G.M[i] - 1;
+            dm[i] = lo[i] ? 0 : G.S[i];
+            dp[i] = hi[i] ? 0 : G.S[i];
+        }
+        const int at = res_at<D>(G, n);
         auto X = [&](int idx) -> T {
-            if constexpr (OP == OP_STAGE2) return X0[li(idx)] + av * X1[li(idx)];
-            else return X0[li(idx)];
+            if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
+            else return X0[idx];
         };
-        auto nb2 = [&](int i, int si, int k, int sk) -> T {
-            if ((si < 0 && j[i] == 1) || (sk < 0 && j[k] == 1)) return T(0);
-            return X(n + si * (1 << G.S[i]) + sk * (1 << G.S[k]));
-        };
-        const T c0 = X(n);
+        const T c0 = X(at);
         T xm[D], xp[D], tmix[D], tphi[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const int E = 1 << G.S[i];
-            xm[i] = (j[i] == 1) ? T(0) : X(n - E);
-            xp[i] = (j[i] == G.M[i]) ? xm[i] : X(n + E);
+            const T a = X(at - dm[i]);
+            const T b = X(at + dp[i]);
+            xm[i] = lo[i] ? T(0) : a;
+            xp[i] = hi[i] ? xm[i] : b;
         }
-        const T* tV = tab + U.tab[D - 1];
-        const T vsq = tV[j[D - 1] - 1];
-        T acc = tV[G.MV] * (xp[D - 1] - T(2) * c0 + xm[D - 1]);
-        tmix[D - 1] = tV[G.MV + 1];
+        const T vsq = tv[j[D - 1]];
+        T acc = tdV * (xp[D - 1] - T(2) * c0 + xm[D - 1]);
+        tmix[D - 1] = tmixV;
         tphi[D - 1] = T(0);
 #pragma unroll
         for (int i = 0; i < D - 1; ++i) {
-            const T* ti = tab + U.tab[i];
-            tmix[i] = ti[G.M[i] + j[i] - 1];
-            tphi[i] = ti[2 * G.M[i] + j[i] - 1];
-            acc += ti[j[i] - 1] * (xp[i] - T(2) * c0 + xm[i]);
+            const T* ti = st + G.tb[i];
+            tmix[i] = ti[G.M[i] + j[i]];
+            tphi[i] = ti[2 * G.M[i] + j[i]];
+            acc += ti[j[i]] * (xp[i] - T(2) * c0 + xm[i]);
         }
 #pragma unroll
         for (int i = 0; i < D - 1; ++i) {
 #pragma unroll
             for (int k = i + 1; k < D; ++k) {
-                if (j[i] != G.M[i] && j[k] != G.M[k]) {
-                    const T xx = nb2(i, 1, k, 1) + nb2(i, -1, k, -1) - nb2(i, 1, k, -1) - nb2(i, -1, k, 1);
-                    const T cik = (k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i];
-                    acc += cik * tmix[i] * tmix[k] * xx;
-                }
+                const T pp = X(at + dp[i] + dp[k]);
+                const T mm = X(at - dm[i] - dm[k]);
+                const T pm = X(at + dp[i] - dm[k]);
+                const T mp = X(at - dm[i] + dp[k]);
+                const T xx = pp + ((lo[i] || lo[k]) ? T(0) : mm) - (lo[k] ? T(0) : pm) - (lo[i] ? T(0) : mp);
+                const T cik = (k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i];
+                const T cf = (hi[i] || hi[k]) ? T(0) : cik * tmix[i] * tmix[k];
+                acc += cf * xx;
             }
         }
 #pragma unroll
         for (int i = 1; i < D - 1; ++i) {
-            if (j[i] != G.M[i]) {
-                T sacc = T(0);
+            T sacc = T(0);
 #pragma unroll
-                for (int jj = 1; jj <= i; ++jj) sacc += cst[CST_RHO + i * MAXD + jj] * tphi[jj];
-                acc += tmix[i] * sacc * (xp[i] - xm[i]);
-            }
+            for (int jj = 1; jj <= i; ++jj) sacc += cst[CST_RHO + i * MAXD + jj] * tphi[jj];
+            const T ca = hi[i] ? T(0) : tmix[i] * sacc;
+            acc += ca * (xp[i] - xm[i]);
         }
         bool face = false;                       // Dirichlet rate faces: null rows
 #pragma unroll
-        for (int i = 0; i < D - 1; ++i) face |= dir_face(dirichlet, j[i], G.M[i]);
+        for (int i = 0; i < D - 1; ++i) face |= dir_face(dirichlet, j[i] + 1, G.M[i]);
         const T F = face ? T(0) : vsq * acc;
-        const int ln = li(n);
-        if constexpr (OP == OP_STAGE1) Wout[ln] = sc * (F + cGg[n]);
-        else if constexpr (OP == OP_STAGE2) Wout[ln] = sc * (F + cGg[n]) + qv * X1[ln];
-        else Wout[ln] = T(2) * Wout[ln] - X0[ln] + sc * F;
+        if constexpr (OP == OP_STAGE1) Wout[at] = sc * (F + cGg[n]);
+        else if constexpr (OP == OP_STAGE2) Wout[at] = sc * (F + cGg[n]) + qv * X1[at];
+        else Wout[at] = T(2) * Wout[at] - c0 + sc * F;
     }
 }
 
@@ -1379,35 +1399,32 @@ __device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const UnitDev& 
 // (I - nu dt A_ax) for this unit's levels and the line's j_V, as the streaming sweeps use); with
 // `upd` the result x updates W += b1 K1 + b2 x instead of being stored.
 template <typename T, int D>
-__device__ __forceinline__ void res_strided(const ResGeom<D>& G, const UnitDev& U, const T* fac, int ax,
-                                            const T* in, T* io, bool upd, T* sW, const T* sK, T b1, T b2)
+__device__ __forceinline__ void res_strided(const ResGeom<D>& G, const T* fa, int ax, const T* in, T* io, bool upd,
+                                            T* sW, const T* sK, T b1, T b2)
 {
-    const int Mi = G.M[ax], Si = G.S[ax], E = 1 << Si;
-    const int lines = G.Pn / Mi;
+    const int Mi = G.M[ax], Ni = G.N[ax], St = G.S[ax];
+    const int lines = G.Pn >> G.L[ax];
     const bool isV = ax == D - 1;
-    const T* fa = fac + U.fac[ax];
     for (int line = threadIdx.x; line < lines; line += RES_BLOCK) {
-        const int lo = line & (E - 1), hi = line >> Si;
-        const int base = lo + (hi << (Si + U.lv[ax]));
-        const T* f = isV ? fa : fa + (int64_t)((base >> G.SV) & (G.MV - 1)) * 3 * Mi;
+        const int lo = line & ((1 << Ni) - 1), hi = line >> Ni;
+        const int base = lo + (hi << (Ni + G.L[ax]));          // node index of the line's first row
+        const T* f = isV ? fa : fa + (int64_t)((base >> G.N[D - 1]) & (G.MV - 1)) * 3 * Mi;
+        int a = res_at<D>(G, base);
         T dprev = T(0);
 #pragma unroll 4
-        for (int r = 0; r < Mi; ++r) {
-            const int idx = li(base + r * E);
-            dprev = in[idx] * f[r] - f[Mi + r] * dprev;
-            io[idx] = dprev;
+        for (int r = 0; r < Mi; ++r, a += St) {
+            dprev = in[a] * f[r] - f[Mi + r] * dprev;
+            io[a] = dprev;
         }
-        T x = dprev;                            // c'_{M-1} = 0: x_{M-1} = d'_{M-1}
-        if (upd) {
-            const int idx = li(base + (Mi - 1) * E);
-            sW[idx] = sW[idx] + b1 * sK[idx] + b2 * x;
-        }
+        a -= St;                                 // row M - 1
+        T x = dprev;                             // c'_{M-1} = 0: x_{M-1} = d'_{M-1}
+        if (upd) sW[a] = sW[a] + b1 * sK[a] + b2 * x;
 #pragma unroll 4
         for (int r = Mi - 2; r >= 0; --r) {
-            const int idx = li(base + r * E);
-            x = io[idx] - f[2 * Mi + r] * x;
-            if (upd) sW[idx] = sW[idx] + b1 * sK[idx] + b2 * x;
-            else io[idx] = x;
+            a -= St;
+            x = io[a] - f[2 * Mi + r] * x;
+            if (upd) sW[a] = sW[a] + b1 * sK[a] + b2 * x;
+            else io[a] = x;
         }
     }
 }
@@ -1415,12 +1432,12 @@ __device__ __forceinline__ void res_strided(const ResGeom<D>& G, const UnitDev& 
 // The AMF chain (I - nu dt A_1) .. (I - nu dt A_d) on LDS vectors: axis 0 reads src, the others
 // work in place on dst; with upd the last solve ends in W += b1 K1 + b2 K2.
 template <typename T, int D>
-__device__ __forceinline__ void res_chain(const ResGeom<D>& G, const UnitDev& U, const T* fac,
-                                          const T* src, T* dst, bool upd, T* sW, const T* sK, T b1, T b2)
+__device__ __forceinline__ void res_chain(const ResGeom<D>& G, const T* const (&fa)[D], const T* src, T* dst,
+                                          bool upd, T* sW, const T* sK, T b1, T b2)
 {
 #pragma unroll
     for (int ax = 0; ax < D; ++ax) {
-        res_strided<T, D>(G, U, fac, ax, ax == 0 ? src : dst, dst, upd && ax == D - 1, sW, sK, b1, b2);
+        res_strided<T, D>(G, fa[ax], ax, ax == 0 ? src : dst, dst, upd && ax == D - 1, sW, sK, b1, b2);
         __syncthreads();
     }
 }
@@ -1435,19 +1452,24 @@ __global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
         int sh = 0;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
+            G.L[i] = U.lv[i];
             G.M[i] = 1 << U.lv[i];
-            G.S[i] = sh;
+            G.N[i] = sh;
             sh += U.lv[i];
         }
         G.Pn = 1 << U.lsum;
-        G.SV = G.S[D - 1];
         G.MV = G.M[D - 1];
+        G.P0 = res_pitch(G.M[0]);
+        G.S[0] = 1;
+#pragma unroll
+        for (int i = 1; i < D; ++i) G.S[i] = (i == 1 ? G.P0 : G.S[i - 1] * G.M[i - 1]);
     }
     const int LP = A.lds_len;
     T* sW = (T*)res_smem;
     T* sK = sW + LP;
     T* sA = sK + LP;
     T* sB = sA + LP;
+    T* st = sB + LP;                              // the unit's coefficient tables
     T* Wg = (T*)A.W + U.off;
     const T* cGg = (const T*)A.cG + U.off;
     const T* tab = (const T*)P.tab;
@@ -1456,30 +1478,40 @@ __global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
     const T dt = cst[CST_RUN + 3 * A.run], thdt = cst[CST_RUN + 3 * A.run + 2];
     const T a21 = (T)A.a21, q21 = (T)A.q21, b1 = (T)A.b1, b2 = (T)A.b2;
     const T* fac = (const T*)P.fac + (int64_t)A.run * P.fac_run_stride;
-    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) sW[li(n)] = Wg[n];
-    __syncthreads();
-    for (int st = 0; st < A.nsteps; ++st) {
-        // stage 1: K^(0) = dt F(Y); chain; refinement; chain -> K1
-        res_stencil<T, D, OP_STAGE1>(G, U, tab, cst, dirp, dt, T(0), T(0), sW, nullptr, sA, cGg);
-        __syncthreads();
-        res_chain<T, D>(G, U, fac, sA, sB, false, sW, sK, b1, b2);
-        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, dirp, thdt, T(0), T(0), sB, nullptr, sA, cGg);
-        __syncthreads();
-        res_chain<T, D>(G, U, fac, sA, sK, false, sW, sK, b1, b2);
-        // stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1; chain; refinement; chain ending in the update
-        res_stencil<T, D, OP_STAGE2>(G, U, tab, cst, dirp, dt, a21, q21, sW, sK, sA, cGg);
-        __syncthreads();
-        res_chain<T, D>(G, U, fac, sA, sB, false, sW, sK, b1, b2);
-        res_stencil<T, D, OP_REFINE>(G, U, tab, cst, dirp, thdt, T(0), T(0), sB, nullptr, sA, cGg);
-        __syncthreads();
-        res_chain<T, D>(G, U, fac, sA, sB, true, sW, sK, b1, b2);
+    const T* fa[D];
+    {
+        int at = 0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int len = i < D - 1 ? 3 * G.M[i] : G.MV + 2;
+            const T* src = tab + U.tab[i];
+            for (int q = threadIdx.x; q < len; q += RES_BLOCK) st[at + q] = src[q];
+            G.tb[i] = at;
+            at += len;
+            fa[i] = fac + U.fac[i];
+        }
     }
-    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) Wg[n] = sW[li(n)];
+    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) sW[res_at<D>(G, n)] = Wg[n];
+    __syncthreads();
+    for (int s = 0; s < A.nsteps; ++s) {
+        // stage 1: K^(0) = dt F(Y); chain; refinement; chain -> K1
+        res_stencil<T, D, OP_STAGE1>(G, st, cst, dirp, dt, T(0), T(0), sW, nullptr, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, fa, sA, sB, false, sW, sK, b1, b2);
+        res_stencil<T, D, OP_REFINE>(G, st, cst, dirp, thdt, T(0), T(0), sB, nullptr, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, fa, sA, sK, false, sW, sK, b1, b2);
+        // stage 2: K^(0) = dt F(Y + a21 K1) + q21 K1; chain; refinement; chain ending in the update
+        res_stencil<T, D, OP_STAGE2>(G, st, cst, dirp, dt, a21, q21, sW, sK, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, fa, sA, sB, false, sW, sK, b1, b2);
+        res_stencil<T, D, OP_REFINE>(G, st, cst, dirp, thdt, T(0), T(0), sB, nullptr, sA, cGg);
+        __syncthreads();
+        res_chain<T, D>(G, fa, sA, sB, true, sW, sK, b1, b2);
+    }
+    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) Wg[n] = sW[res_at<D>(G, n)];
 }
 
-// ------------------------------------------------------------------------------------------------
-// u_l(x_eval): tensor-product linear interpolation of Y = W + g, cell min(floor(x/h), M-1); corners
-// on a lower face carry W = 0.  One thread per unit, FP64.
 template <typename T>
 __global__ void k_unit_values(DevPlan P, const T* W, double* vals)
 {
@@ -1973,7 +2005,7 @@ template <typename T>
 static hipError_t resident_t(const DevPlan& P, const ResArgs& a, hipStream_t s)
 {
     dim3 g((unsigned)P.n_units), b(RES_BLOCK);
-    const size_t shm = (size_t)4 * a.lds_len * sizeof(T);
+    const size_t shm = ((size_t)4 * a.lds_len + (size_t)a.tab_len) * sizeof(T);
     switch (P.d) {
     case 2: hipLaunchKernelGGL((k_resident<T, 2>), g, b, shm, s, P, a); break;
     case 3: hipLaunchKernelGGL((k_resident<T, 3>), g, b, shm, s, P, a); break;
