@@ -11,6 +11,7 @@
 namespace amf {
 
 constexpr int NODE_BLOCK = 256;    // threads per block of the per-node kernels
+constexpr int WAVE = 64;           // lanes of a wavefront
 constexpr int LINE_BLOCK = 256;    // threads per block of the sweep kernels
 constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines

@@ -1137,16 +1137,14 @@ __device__ __forceinline__ Contig contig_geom(const DevPlan& P, const UnitDev& U
     return C;
 }
 
-// Short contiguous line: one thread, Thomas with the line in VGPRs.  in/out: the line's M
-// consecutive values (may alias), td: its tdiff factors, cm = V^2 of the line; dir: the last row
-// sits on a Dirichlet face (identity row: zero coupling).
+// Short contiguous line: one thread, Thomas with the line in VGPRs.  g: the line's M values (solved
+// in place), td: its tdiff factors, cm = V^2 of the line; dir: the last row sits on a Dirichlet face
+// (identity row: zero coupling).
 template <typename T, int LM>
-__device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm, T nudt, bool dir)
+__device__ __forceinline__ void reg_solve(T (&g)[1 << LM], const T* td, T cm, T nudt, bool dir)
 {
     constexpr int M = 1 << LM;
-    T g[M], cp[M];
-#pragma unroll
-    for (int r = 0; r < M; ++r) g[r] = in[r];
+    T cp[M];
 #pragma unroll
     for (int r = 0; r < M; ++r) {
         const T nd = (dir && r == M - 1) ? T(0) : nudt * (td[r] * cm);
@@ -1159,14 +1157,80 @@ __device__ __forceinline__ void reg_solve(const T* in, T* out, const T* td, T cm
     }
 #pragma unroll
     for (int r = M - 2; r >= 0; --r) g[r] = g[r] - cp[r] * g[r + 1];
-#pragma unroll
-    for (int r = 0; r < M; ++r) out[r] = g[r];
 }
 
-template <typename T, int LM>
-__device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Contig& L, T nudt)
+// Wavefront-cooperative transfer of per-lane chunks of CH consecutive elements (CH * sizeof(T) a
+// multiple of 16 bytes, chunks 16-byte aligned): the wavefront's 64 chunks move as 16-byte pieces,
+// consecutive lanes on consecutive pieces, through the wavefront's LDS tile (rows of CH elements at
+// a pitch of CH + one piece), so every global access instruction covers whole cache lines instead of
+// one 16-byte piece of 64 different lines.  base: this lane's chunk (element index); ok: the lane
+// has a chunk.  Every thread of the block calls these (they contain block barriers).
+template <typename T, int CH>
+struct ChunkTile {
+    static constexpr int VPP = 16 / (int)sizeof(T);   // elements per 16-byte piece
+    static constexpr int PPC = CH / VPP;             // pieces per chunk (a power of two)
+    static constexpr int PITCH = CH + VPP;           // elements per tile row
+    static_assert(CH % VPP == 0, "chunks of whole 16-byte pieces");
+};
+using piece_t = unsigned int __attribute__((ext_vector_type(4)));
+
+template <typename T, int CH>
+__device__ __forceinline__ void chunk_load(const T* g, int64_t base, bool ok, T* tile, T (&x)[CH])
 {
-    reg_solve<T, LM>((const T*)A.in + L.base, (T*)A.out + L.base, (const T*)L.tdiff, (T)L.vsq, nudt, L.dir != 0);
+    using C = ChunkTile<T, CH>;
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int it = 0; it < C::PPC; ++it) {
+        const int q = it * WAVE + lane;
+        const int row = q / C::PPC, pc = q % C::PPC;
+        const int64_t b = __shfl(base, row);
+        const int rok = __shfl(ok ? 1 : 0, row);
+        if (rok) *(piece_t*)(tile + row * C::PITCH + pc * C::VPP) = *(const piece_t*)(g + b + pc * C::VPP);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < CH; ++r) x[r] = tile[lane * C::PITCH + r];
+}
+
+template <typename T, int CH>
+__device__ __forceinline__ void chunk_store(T* g, int64_t base, bool ok, T* tile, const T (&x)[CH])
+{
+    using C = ChunkTile<T, CH>;
+    const int lane = threadIdx.x & (WAVE - 1);
+    __syncthreads();                                  // every lane has read its row of the tile
+#pragma unroll
+    for (int r = 0; r < CH; ++r) tile[lane * C::PITCH + r] = x[r];
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < C::PPC; ++it) {
+        const int q = it * WAVE + lane;
+        const int row = q / C::PPC, pc = q % C::PPC;
+        const int64_t b = __shfl(base, row);
+        const int rok = __shfl(ok ? 1 : 0, row);
+        if (rok) *(piece_t*)(g + b + pc * C::VPP) = *(const piece_t*)(tile + row * C::PITCH + pc * C::VPP);
+    }
+}
+
+// One thread per short line: the line moves through the tile when it spans whole 16-byte pieces,
+// else with plain loads and stores.
+template <typename T, int LM>
+__device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Contig& L, T nudt, bool ok, T* tile)
+{
+    constexpr int M = 1 << LM;
+    T g[M];
+    if constexpr (M * sizeof(T) % 16 == 0) {
+        chunk_load<T, M>((const T*)A.in, L.base, ok, tile, g);
+        if (ok) reg_solve<T, LM>(g, (const T*)L.tdiff, (T)L.vsq, nudt, L.dir != 0);
+        chunk_store<T, M>((T*)A.out, L.base, ok, tile, g);
+    } else if (ok) {
+        const T* in = (const T*)A.in + L.base;
+#pragma unroll
+        for (int r = 0; r < M; ++r) g[r] = in[r];
+        reg_solve<T, LM>(g, (const T*)L.tdiff, (T)L.vsq, nudt, L.dir != 0);
+        T* out = (T*)A.out + L.base;
+#pragma unroll
+        for (int r = 0; r < M; ++r) out[r] = g[r];
+    }
 }
 
 // Long contiguous line: SP = M/SEG lanes, each owning SEG consecutive rows.  Each lane eliminates
@@ -1174,15 +1238,13 @@ __device__ __forceinline__ void sweep_contig_reg(const SweepArgs& A, const Conti
 // row): x_k = y_k + v_k z_{p-1} + w_k z_p.  Substituting into the segment-closing rows leaves a
 // tridiagonal system in z_0..z_{SP-1}, solved by parallel cyclic reduction across the SP lanes with
 // wavefront shuffles; the lanes then reconstruct their rows.  Diagonally dominant: no pivoting.
-// in/out: the lane's SEG rows (contiguous), td: their tdiff factors, cm = V^2 of the line.
+// g: the lane's SEG rows (contiguous), solved in place; td: their tdiff factors, cm = V^2 of the line.
 template <typename T, int SP>
-__device__ __forceinline__ void part_solve(const T* in, T* out, const T* td, T cm, T nudt, int p, bool dir)
+__device__ __forceinline__ void part_solve(T (&g)[SEG], const T* td, T cm, T nudt, int p, bool dir)
 {
     constexpr int S = SEG;
     const bool first = (p == 0), last = (p == SP - 1);
-    T g[S], cp[S - 1], v[S - 1], w[S - 1];
-#pragma unroll
-    for (int k = 0; k < S; ++k) g[k] = in[k];
+    T cp[S - 1], v[S - 1], w[S - 1];
     // interior rows k = 0..S-2 (global r0 + k); row S-1 closes the segment
     T a_first = T(0);
 #pragma unroll
@@ -1243,50 +1305,74 @@ __device__ __forceinline__ void part_solve(const T* in, T* out, const T* td, T c
     T zprev = __shfl_up(z, 1, SP);
     if (first) zprev = T(0);
 #pragma unroll
-    for (int k = 0; k < S - 1; ++k) out[k] = g[k] + v[k] * zprev + w[k] * z;
-    out[S - 1] = z;
+    for (int k = 0; k < S - 1; ++k) g[k] = g[k] + v[k] * zprev + w[k] * z;
+    g[S - 1] = z;
 }
 
+// The lane's SEG rows move through the wavefront's tile in FP32; in FP64 the tile costs more in
+// occupancy (the solve holds four SEG-row arrays) than it gains, and the rows are loaded directly.
 template <typename T, int SP>
-__device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Contig& L, T nudt, int p)
+__device__ __forceinline__ void sweep_contig_part(const SweepArgs& A, const Contig& L, T nudt, int p, bool ok, T* tile)
 {
     const int r0 = p * SEG;
-    part_solve<T, SP>((const T*)A.in + L.base + r0, (T*)A.out + L.base + r0, (const T*)L.tdiff + r0,
-                      (T)L.vsq, nudt, p, L.dir != 0);
+    T g[SEG];
+    if constexpr (sizeof(T) == 4) {
+        chunk_load<T, SEG>((const T*)A.in, L.base + r0, ok, tile, g);
+        if (ok) part_solve<T, SP>(g, (const T*)L.tdiff + r0, (T)L.vsq, nudt, p, L.dir != 0);   // whole lane groups
+        chunk_store<T, SEG>((T*)A.out, L.base + r0, ok, tile, g);
+    } else if (ok) {
+        const T* in = (const T*)A.in + L.base + r0;
+#pragma unroll
+        for (int k = 0; k < SEG; ++k) g[k] = in[k];
+        part_solve<T, SP>(g, (const T*)L.tdiff + r0, (T)L.vsq, nudt, p, L.dir != 0);
+        T* out = (T*)A.out + L.base + r0;
+#pragma unroll
+        for (int k = 0; k < SEG; ++k) out[k] = g[k];
+    }
 }
 
 template <typename T, bool LONG>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_contig(DevPlan P, SweepArgs A, int64_t blk0)
 {
+    // one tile per wavefront, sized for chunks of 16 elements (the longest: SEG rows, or a line of
+    // 2^CONTIG_REG_LM points)
+    static_assert(SEG <= 16 && (1 << CONTIG_REG_LM) <= 16, "chunks fit the tile");
+    constexpr int TILE = (LONG && sizeof(T) == 8) ? 1 : WAVE * ChunkTile<T, 16>::PITCH;   // FP64 long: no tile
+    __shared__ __align__(16) T tiles[LINE_BLOCK / WAVE][TILE];
     const SweepBlk B = P.ax_blk[0][blk0 + xcd_block(blockIdx.x, gridDim.x, P.xcd == 2)];
     const int lm = B.lm;
     const int sp = lm > CONTIG_REG_LM ? (1 << lm) / SEG : 1;   // lanes per line
     const int64_t gl = B.line_start + threadIdx.x / sp;
-    if (gl >= B.line_end) return;                              // whole lane groups drop out
+    const bool ok = gl < B.line_end;        // lanes past the block's lines stay for the barriers
     const int p = threadIdx.x & (sp - 1);
-    const int64_t* lo = P.ax_line_off[0];
-    int k = B.k_start;
-    while (gl >= lo[k + 1]) ++k;
-    const UnitDev U = P.units[P.ax_units[0][k]];
-    const Contig L = contig_geom<T>(P, U, gl - lo[k], lm);
-    const T nudt = ((const T*)P.tab)[P.probs[U.prob].cst + CST_RUN + 3 * A.run + 1];
+    Contig L{};
+    T nudt = T(0);
+    if (ok) {
+        const int64_t* lo = P.ax_line_off[0];
+        int k = B.k_start;
+        while (gl >= lo[k + 1]) ++k;
+        const UnitDev& U = P.units[P.ax_units[0][k]];
+        L = contig_geom<T>(P, U, gl - lo[k], lm);
+        nudt = ((const T*)P.tab)[P.probs[U.prob].cst + CST_RUN + 3 * A.run + 1];
+    }
+    T* tile = tiles[threadIdx.x / WAVE];
     if constexpr (!LONG) {
         switch (lm) {
-        case 0: sweep_contig_reg<T, 0>(A, L, nudt); break;
-        case 1: sweep_contig_reg<T, 1>(A, L, nudt); break;
-        case 2: sweep_contig_reg<T, 2>(A, L, nudt); break;
-        case 3: sweep_contig_reg<T, 3>(A, L, nudt); break;
-        case 4: sweep_contig_reg<T, 4>(A, L, nudt); break;
+        case 0: sweep_contig_reg<T, 0>(A, L, nudt, ok, tile); break;
+        case 1: sweep_contig_reg<T, 1>(A, L, nudt, ok, tile); break;
+        case 2: sweep_contig_reg<T, 2>(A, L, nudt, ok, tile); break;
+        case 3: sweep_contig_reg<T, 3>(A, L, nudt, ok, tile); break;
+        case 4: sweep_contig_reg<T, 4>(A, L, nudt, ok, tile); break;
         default: break;
         }
     } else {
         switch (lm) {
-        case 5: sweep_contig_part<T, 2>(A, L, nudt, p); break;
-        case 6: sweep_contig_part<T, 4>(A, L, nudt, p); break;
-        case 7: sweep_contig_part<T, 8>(A, L, nudt, p); break;
-        case 8: sweep_contig_part<T, 16>(A, L, nudt, p); break;
-        case 9: sweep_contig_part<T, 32>(A, L, nudt, p); break;
-        case 10: sweep_contig_part<T, 64>(A, L, nudt, p); break;
+        case 5: sweep_contig_part<T, 2>(A, L, nudt, p, ok, tile); break;
+        case 6: sweep_contig_part<T, 4>(A, L, nudt, p, ok, tile); break;
+        case 7: sweep_contig_part<T, 8>(A, L, nudt, p, ok, tile); break;
+        case 8: sweep_contig_part<T, 16>(A, L, nudt, p, ok, tile); break;
+        case 9: sweep_contig_part<T, 32>(A, L, nudt, p, ok, tile); break;
+        case 10: sweep_contig_part<T, 64>(A, L, nudt, p, ok, tile); break;
         default: break;   // longer lines go to k_sweep_strided_long
         }
     }
