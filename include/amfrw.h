@@ -235,14 +235,17 @@ amf_status amf_axis_solve(amf_plan* plan, int32_t axis, const void* d_in, void* 
  *                  schedule: one launch per operator / axis over all grids.
  *   fuse_axis0:    streaming schedule only: 1 = the time-loop operator launches also solve the
  *                  axis-1 systems of the first AMF factor (Lemma lema:ls) on the values they
- *                  produce, so no separate axis-1 sweep runs; allowed when stencil_nodes >= 2,
- *                  256 * stencil_nodes >= the longest axis-1 line (fuse_max_axis0 reports that
- *                  line length) and that line has at most 1024 points; 0 = separate axis-1 sweep
- *                  launches.
+ *                  produce.  Without march: no separate axis-1 sweep runs; allowed when
+ *                  stencil_nodes >= 2, 256 * stencil_nodes >= the longest axis-1 line
+ *                  (fuse_max_axis0 reports that line length) and that line has at most 1024
+ *                  points.  With march: the grids whose axis-1 lines have at most 16 points are
+ *                  solved in the operator launches, the others by the axis-1 sweep in place;
+ *                  allowed when every axis-1 line has at most 1024 points.  0 = separate axis-1
+ *                  sweep launches.
  *   march:         streaming schedule, d <= 4 only (march_available): 1 = the time-loop operators
  *                  run plane-tiled, one block per (grid, tile of the axes 1..d-1, range of V
  *                  planes) walking the V axis with the tile's neighbourhood in an LDS ring of
- *                  planes (every stencil neighbour read from LDS); excludes fuse_axis0.
+ *                  planes (every stencil neighbour read from LDS).
  * amf_schedule_set may be called at any time between enqueued calls; AMF_E_INVALID otherwise. */
 typedef struct {
     uint32_t struct_size;

@@ -35,6 +35,9 @@ def candidates(plan):
     if sc["march_available"]:
         out += [dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=x, resident=0, fuse_axis0=0, march=1)
                 for x in (0, 1, 2)]
+        if sc["fuse_max_axis0"] <= 1024:
+            out += [dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=x, resident=0, fuse_axis0=1, march=1)
+                    for x in (0, 1)]
     if sc["resident_available"]:
         out.append(dict(stencil_nodes=sc["stencil_nodes"], xcd_remap=0, resident=1, fuse_axis0=0, march=0))
     return out

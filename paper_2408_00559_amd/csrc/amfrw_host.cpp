@@ -1015,9 +1015,10 @@ hipError_t run_stencil(amf_plan* P, int op, const StencilArgs& a, hipStream_t s)
 {
     // vectors read or written once: F only 2; stage 1 (W, F(g), out) 3; stage 2 (W, K1, F(g), out)
     // 4; refinement (K^(d), K^(0) in and out) 3; the fused stage operators also write the solved
-    // values (one more vector), the fused refinement writes only those
+    // values (one more vector; with the marching operator, of the grids with short axis-1 lines
+    // only), the fused refinement writes only those
     double nv = (op == OP_F_PAYOFF || op == OP_F_ZERO) ? 2.0 : (op == OP_STAGE2 ? 4.0 : 3.0);
-    if (a.S != nullptr && op != OP_REFINE) nv += 1.0;
+    if (a.S != nullptr && op != OP_REFINE) nv += P->march ? P->ax_short_frac[0] : 1.0;
     const int kc = op == OP_STAGE1 ? AMF_K_STAGE1 : op == OP_STAGE2 ? AMF_K_STAGE2
                  : op == OP_REFINE ? AMF_K_REFINE : AMF_K_OPERATOR;
     return timed(P, kc, nv * P->vbytes(), s, [&] { return launch_stencil(P->dev, P->prec, op, a, s); });
@@ -1025,10 +1026,11 @@ hipError_t run_stencil(amf_plan* P, int op, const StencilArgs& a, hipStream_t s)
 
 // Both launches (short and long lines) of one directional solve.  Algorithmic bytes: the part's
 // share of the vector read and written once (four vectors for the update form).
-hipError_t run_sweep(amf_plan* P, int axis, int epi, const SweepArgs& a, hipStream_t s)
+// part0 = false skips the short-line launch (axis 0 with the marching operator's fused solve).
+hipError_t run_sweep(amf_plan* P, int axis, int epi, const SweepArgs& a, hipStream_t s, bool part0 = true)
 {
     const bool up = epi == EPI_UPDATE;
-    for (int part = 0; part < 2; ++part) {
+    for (int part = part0 ? 0 : 1; part < 2; ++part) {
         const double share = part == 0 ? P->ax_short_frac[axis] : 1.0 - P->ax_short_frac[axis];
         if (share <= 0.0) continue;
         const int kc = axis == 0 ? (part ? AMF_K_SWEEP_CONTIG_LONG : AMF_K_SWEEP_CONTIG)
@@ -1122,7 +1124,10 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
     auto ca = [&](int r, int j) { return P->sch.a[r * AMF_MAX_STAGES + j]; };
     auto cq = [&](int r, int j) { return P->sch.q[r * AMF_MAX_STAGES + j]; };
     const bool fuse = P->fuse0 != 0 && !lower;
-    const int first = fuse ? 1 : 0;
+    // the marching operator fuses the axis-1 solve of the units with short axis-1 lines only: the
+    // chain then starts at axis 0 with the long-line launch, in place over the operator's output
+    const bool mfuse = fuse && P->march;
+    const int first = fuse && !mfuse ? 1 : 0;
     hipError_t e;
     // (I - nu dt A_1) .. (I - nu dt A_d) applied in axis order from axis `first` (1 when the operator
     // launch already solved axis 0); the first solve reads `in`, the others work in place on `dst`;
@@ -1141,7 +1146,7 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
                 a.b1 = b1;
                 a.b2 = b2;
             }
-            hipError_t err = run_sweep(P, ax, epi, a, s);
+            hipError_t err = run_sweep(P, ax, epi, a, s, !(mfuse && ax == 0));
             if (err != hipSuccess) return err;
         }
         return hipSuccess;
@@ -1201,7 +1206,7 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
             }
             continue;
         }
-        if ((e = chain(fuse ? B : A, B, false, nullptr, 0.0, 0.0)) != hipSuccess) return hip_fail(e, "sweep");
+        if ((e = chain(fuse && !mfuse ? B : A, B, false, nullptr, 0.0, 0.0)) != hipSuccess) return hip_fail(e, "sweep");
         // Khat^(0) = 2 K^(0) - K^(d) + theta dt F(K^(d)) -> A; fused: its axis-0 solve -> dst (the last
         // stage's goes back over A, which no other block reads)
         void* dst = last ? (fuse ? A : B) : K(r);
@@ -1213,7 +1218,7 @@ amf_status one_step(amf_plan* P, int run, hipStream_t s)
         st.scale_sel = sel_th;
         if ((e = run_stencil(P, OP_REFINE, st, s)) != hipSuccess) return hip_fail(e, "stencil");
         if (!last) {
-            if ((e = chain(fuse ? dst : A, dst, false, nullptr, 0.0, 0.0)) != hipSuccess) return hip_fail(e, "sweep");
+            if ((e = chain(fuse && !mfuse ? dst : A, dst, false, nullptr, 0.0, 0.0)) != hipSuccess) return hip_fail(e, "sweep");
             continue;
         }
         // the last chain ends in W += sum_{j<s} b_j K_j + b_s K_s: for s = 2 the sum is b_1 K_1
@@ -1572,12 +1577,14 @@ amf_status amf_schedule_set(amf_plan* P, const amf_schedule* sc)
     if (sc->fuse_axis0 != 0 && sc->fuse_axis0 != 1) return fail(AMF_E_INVALID, "fuse_axis0 must be 0 or 1");
     if (sc->fuse_axis0 && P->sch.w_matrix != AMF_W_AMF)
         return fail(AMF_E_INVALID, "fuse_axis0 applies to the AMF W only");
-    if (sc->fuse_axis0 && (r < 2 || r > P->min_m0 || NODE_BLOCK * r < P->max_m0 || P->max_m0 > (1 << CONTIG_PART_LM)))
-        return fail(AMF_E_INVALID, "fuse_axis0 needs 2 <= stencil_nodes <= the shortest axis-1 line and 256 * "
-                                   "stencil_nodes >= the longest one (at most 1024 points)");
     if (sc->march != 0 && sc->march != 1) return fail(AMF_E_INVALID, "march must be 0 or 1");
     if (sc->march && P->march_blk.empty()) return fail(AMF_E_INVALID, "the marching operator needs d <= 4");
-    if (sc->march && sc->fuse_axis0) return fail(AMF_E_INVALID, "the marching operator does not fuse the axis-1 solve");
+    if (sc->fuse_axis0 && !sc->march &&
+        (r < 2 || r > P->min_m0 || NODE_BLOCK * r < P->max_m0 || P->max_m0 > (1 << CONTIG_PART_LM)))
+        return fail(AMF_E_INVALID, "fuse_axis0 needs 2 <= stencil_nodes <= the shortest axis-1 line and 256 * "
+                                   "stencil_nodes >= the longest one (at most 1024 points)");
+    if (sc->fuse_axis0 && sc->march && P->max_m0 > (1 << CONTIG_PART_LM))
+        return fail(AMF_E_INVALID, "fuse_axis0 with the marching operator needs axis-1 lines of at most 1024 points");
     if (r != P->stencil_r || sc->xcd_remap != P->xcd || sc->resident != P->resident || sc->fuse_axis0 != P->fuse0 ||
         sc->march != P->march)
         P->drop_graph();

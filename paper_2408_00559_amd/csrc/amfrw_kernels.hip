@@ -579,6 +579,70 @@ struct GpuMem {
     __device__ __forceinline__ void sw(int i, T v) const { lds[i] = v; }
 };
 
+// DPP row shifts inside rows of 16 lanes: row_shr:K gives lane i the value of lane i - K of its row,
+// row_shl:K that of lane i + K (0 from outside the row).  Register moves only.
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF, 0xF, false);
+    const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+constexpr int DPP_ROW_SHL = 0x100, DPP_ROW_SHR = 0x110;
+
+// Solves a tridiagonal system of M <= 16 rows held one row per lane in M consecutive lanes (the
+// group aligned inside a 16-lane row; r = the lane's row) with the tabulated Thomas factors of its
+// row (Lemma lema:ls): forward d'_r = g_r inv_r - (a inv)_r d'_{r-1}, backward x_r = d'_r -
+// c'_r x_{r+1}.  Each recurrence is affine, y_r = alpha_r + beta_r y_{r -/+ 1}, and is evaluated by
+// a scan of log2(M) steps, composing the maps of lanes K apart.
+template <int K, typename T>
+__device__ __forceinline__ void scan_down(T& al, T& be, int r, int M)
+{
+    if (K < M) {
+        const T pa = dpp_move<DPP_ROW_SHR + K>(al), pb = dpp_move<DPP_ROW_SHR + K>(be);
+        if (r >= K) {
+            al = al + be * pa;
+            be = be * pb;
+        }
+    }
+}
+
+template <int K, typename T>
+__device__ __forceinline__ void scan_up(T& al, T& be, int r, int M)
+{
+    if (K < M) {
+        const T na = dpp_move<DPP_ROW_SHL + K>(al), nb = dpp_move<DPP_ROW_SHL + K>(be);
+        if (r + K < M) {
+            al = al + be * na;
+            be = be * nb;
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T row_solve(T g, T inv, T ainv, T cp, int r, int M)
+{
+    T al = g * inv, be = -ainv;
+    scan_down<1>(al, be, r, M);
+    scan_down<2>(al, be, r, M);
+    scan_down<4>(al, be, r, M);
+    scan_down<8>(al, be, r, M);
+    T bl = al, bb = -cp;
+    scan_up<1>(bl, bb, r, M);
+    scan_up<2>(bl, bb, r, M);
+    scan_up<4>(bl, bb, r, M);
+    scan_up<8>(bl, bb, r, M);
+    return bl;
+}
+
 // One block.  Per step: plane j_V + 2 (loaded MARCH_DEPTH steps before) into its slot, plane
 // j_V + 2 + MARCH_DEPTH and the next node's stage values loaded, plane j_V computed and stored.  Loads
 // are issued in the order they are waited for, so no wait covers a load issued later in the same
@@ -613,6 +677,10 @@ __device__ __forceinline__ void march_block(const DevPlan& P, const StencilArgs&
     const T* X2 = A.X2 ? (const T*)A.X2 : X1;
     T* W = (T*)A.W;
     const bool act = t.active;
+    // fused axis-1 solve (uniform over the block): the tile rows are whole axis-1 lines
+    const bool fz = march_fused<D>(G, A.S != nullptr);
+    T* Sv = (T*)A.S;
+    const T* fa0 = (const T*)P.fac + (int64_t)A.run * P.fac_run_stride + U.fac[0];
     // the values the stage combination needs at this thread's node of plane jv
     auto centre = [&](int jv, T (&e)[2], bool live) {
         const int64_t b = march_plane_base<D>(G, jv), n = live ? march_plane_len<D>(G, jv) : 0;
@@ -653,18 +721,32 @@ __device__ __forceinline__ void march_block(const DevPlan& P, const StencilArgs&
         // plane jv + 2 goes into the slot of plane jv - 2, which no thread has read since the
         // barrier before the previous step
         if (jv + 2 <= last) march_stash<T, D, Sh>(G, tid, jv + 2, q, av, m);
+        // factors of the fused solve: issued before the plane prefetch, so that waiting for them does
+        // not wait for the prefetch
+        T finv = T(0), fainv = T(0), fcp = T(0);
+        if (fz && act) {
+            const T* f = fa0 + march_fac_at<T, D>(G, jv, t);
+            finv = f[0];
+            fainv = f[G.M[0]];
+            fcp = f[2 * G.M[0]];
+        }
         march_fetch<T, D, OP>(G, jv + 2 + DP, X0, X1, t, q, m, jv + 2 + DP <= last);
         centre(jv + 1, ce[(k + 1) % 2], s < G.vn);
         const T vsq = march_vsq_of<T, D, Sh>(G, s, m);
+        T o = T(0);
         if (act) {
             if (jv < MV) march_cross<T, D, Sh>(G, t, jv + 1, xw[(k + 2) % 3], m);   // uniform over the block
             const T F = march_F<T, D, Sh>(G, t, jv, vsq, tdV, xw[k % 3], xw[(k + 1) % 3], xw[(k + 2) % 3], m);
             const T c0_ = ce[k % 2][0], c1_ = ce[k % 2][1];
-            T o;
             if constexpr (OP == OP_STAGE1) o = sc * (F + c0_);
             else if constexpr (OP == OP_STAGE2) o = sc * (F + c0_) + qv * c1_;
             else o = T(2) * c0_ - xw[(k + 1) % 3][0] + sc * F;
-            m.pst(m.plane(W, march_plane_base<D>(G, jv), march_plane_len<D>(G, jv)), t.gob, o);
+            // the refinement's unsolved value is not read again when its line is solved here
+            if (!(fz && OP == OP_REFINE)) m.pst(m.plane(W, march_plane_base<D>(G, jv), march_plane_len<D>(G, jv)), t.gob, o);
+        }
+        if (fz) {                                   // every lane takes part in the row scans
+            const T x = row_solve<T>(o, finv, fainv, fcp, t.j[0] - 1, G.M[0]);
+            if (act) m.pst(m.plane(Sv, march_plane_base<D>(G, jv), march_plane_len<D>(G, jv)), t.gob, x);
         }
         __syncthreads();
     };
@@ -687,6 +769,7 @@ __device__ __forceinline__ void march_block(const DevPlan& P, const StencilArgs&
 template <typename T, int D, int OP>
 __global__ __launch_bounds__(MARCH_THREADS) void k_march(DevPlan P, StencilArgs A)
 {
+    static_assert(MARCH_FUSE_LM == SHORT_LM, "the fused units are those of the short axis-1 sweep");
     static_assert(OP == OP_STAGE1 || OP == OP_STAGE2 || OP == OP_REFINE, "zero-face operators only");
     extern __shared__ __align__(16) unsigned char march_smem[];
     const MarchBlk B = (P.xcd ? P.march_blk_x : P.march_blk)[blockIdx.x];
@@ -1933,7 +2016,8 @@ template <typename T, int D>
 static hipError_t stencil_td(const DevPlan& P, int op, const StencilArgs& a, hipStream_t s)
 {
     const bool hot = op == OP_STAGE1 || op == OP_STAGE2 || op == OP_REFINE;
-    if (hot && P.march && a.S == nullptr && P.n_march > 0) return march_td<T, D>(P, op, a, s);
+    // the marching operator solves (with a.S) the axis-1 lines of the grids whose lines fit a tile row
+    if (hot && P.march && P.n_march > 0) return march_td<T, D>(P, op, a, s);
     if (hot && P.stencil_r == 8) return stencil_vec<T, D, 8>(P, op, a, s);
     if (hot && P.stencil_r == 4) return stencil_vec<T, D, 4>(P, op, a, s);
     if (hot && P.stencil_r == 2) return stencil_vec<T, D, 2>(P, op, a, s);

@@ -45,6 +45,7 @@ constexpr int MARCH_DEPTH = 1;          // planes whose loads are in flight duri
 constexpr int MARCH_MAX_PLANE = 1280;   // elements per plane slot (tile plus halo)
 constexpr int MARCH_PF = MARCH_MAX_PLANE / MARCH_THREADS;   // prefetch registers per thread (at most)
 constexpr uint32_t MARCH_NONE = 0x7FFFFFF0u;  // byte offset of a zero element: beyond every plane
+constexpr int MARCH_FUSE_LM = 4;        // fused axis-1 solve: units whose axis-1 lines have <= 2^4 points
 
 // One block of the marching operator.  lt[k] = log2 T_k for the plane axes k < d - 1 (0 beyond);
 // shape = index of the compiled stride set (0: run-time strides).
@@ -380,6 +381,21 @@ __host__ __device__ __forceinline__ void march_face(int dirichlet, MarchThr<T, D
     bool face = false;
     for (int k = 0; k < D - 1; ++k) face = face || (dirichlet && t.top[k]);
     t.fmask = face ? T(0) : T(1);
+}
+
+// Fused axis-1 solve (units with M_1 <= 2^MARCH_FUSE_LM, so a tile row is a whole axis-1 line):
+// element offset of this thread's row in the unit's axis-1 Thomas factor block for V plane jv
+// (1-based).  The block holds, per V plane, inv (M_1), a inv (M_1) and c' (M_1).
+template <typename T, int D, int NPF>
+__host__ __device__ __forceinline__ int march_fac_at(const MarchGeo<D>& G, int jv, const MarchThr<T, D, NPF>& t)
+{
+    return (jv - 1) * 3 * G.M[0] + (t.j[0] - 1);
+}
+
+template <int D>
+__host__ __device__ __forceinline__ bool march_fused(const MarchGeo<D>& G, bool fuse)
+{
+    return fuse && G.M[0] <= (1 << MARCH_FUSE_LM);
 }
 
 // Element range of V plane jv (1-based) of a unit inside a grid vector: its first element and its

@@ -152,7 +152,7 @@ struct CheckedMem {
 template <int D, int OP, class Sh>
 void walk_block(const MarchBlk& B, const int8_t* ul, int64_t uoff, int64_t total, CheckedMem& m, std::vector<double>& X0,
                 std::vector<double>& X1, std::vector<double>& cG, std::vector<double>& X2, std::vector<double>& W,
-                int32_t* writes, Err& err)
+                std::vector<double>& Sv, bool fuse, int32_t* writes, Err& err)
 {
     constexpr int NPF = Sh::NPF;
     // the unit's tables: blocks per axis, then the constant block
@@ -277,17 +277,31 @@ void walk_block(const MarchBlk& B, const int8_t* ul, int64_t uoff, int64_t total
                 if (OP == OP_STAGE1) o = 0.1 * (F + e0);
                 else if (OP == OP_STAGE2) o = 0.1 * (F + e0) + 0.3 * e1;
                 else o = 2.0 * e0 - c0 + 0.1 * F;
-                const CheckedMem::Plane hw = m.plane(W.data(), march_plane_base<D>(G, jv), march_plane_len<D>(G, jv));
-                if (hw.n == 0 || th.gob % sizeof(double) != 0 || (int64_t)(th.gob / sizeof(double)) >= hw.n) {
-                    err("store outside its plane");
-                } else {
+                // fused axis-1 solve: the row's factors lie inside the unit's factor block (M_V planes
+                // of 3 M_1 entries); the refinement then stores only the solved value
+                const bool fz = march_fused<D>(G, fuse);
+                if (fz) {
+                    const int fa = march_fac_at<double, D>(G, jv, th);
+                    const int fsize = 3 * G.M[0] * G.M[D - 1];
+                    if (G.T[0] != G.M[0] || G.o[0] != 0) err("fused block whose tile row is not a whole axis-1 line");
+                    for (int q = 0; q < 3; ++q)
+                        if (fa + q * G.M[0] < 0 || fa + q * G.M[0] >= fsize) err("factor read outside the unit's block");
+                }
+                auto store = [&](std::vector<double>& V, bool count) {
+                    const CheckedMem::Plane hw = m.plane(V.data(), march_plane_base<D>(G, jv), march_plane_len<D>(G, jv));
+                    if (hw.n == 0 || th.gob % sizeof(double) != 0 || (int64_t)(th.gob / sizeof(double)) >= hw.n) {
+                        err("store outside its plane");
+                        return;
+                    }
                     const int64_t g = hw.base + (int64_t)(th.gob / sizeof(double));
                     if (g < m.lo || g >= m.hi) err("global write outside the unit");
                     if (g >= 0 && g < total) {
-                        W[(size_t)g] = o;
-                        writes[g] += 1;
+                        V[(size_t)g] = o;
+                        if (count) writes[g] += 1;
                     }
-                }
+                };
+                if (!(fz && OP == OP_REFINE)) store(W, true);
+                if (fz) store(Sv, OP == OP_REFINE);
             }
             cur[(size_t)t] = nxt[(size_t)t];
         }
@@ -296,8 +310,8 @@ void walk_block(const MarchBlk& B, const int8_t* ul, int64_t uoff, int64_t total
 }
 
 template <int D, int OP>
-int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool xorder, int64_t blk_first,
-        int64_t blk_stride, int64_t* n_blocks_out, int64_t* lds_reads_out, int32_t* writes, Err& err)
+int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool xorder, bool fuse,
+        int64_t blk_first, int64_t blk_stride, int64_t* n_blocks_out, int64_t* lds_reads_out, int32_t* writes, Err& err)
 {
     std::vector<MarchBlk> blocks;
     march_blocks(D, n_units, lv, MAXD, elem, blocks);
@@ -312,7 +326,7 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
         blocks.swap(ordered);
     }
     std::vector<double> X0((size_t)total, 0.5), X1((size_t)total, 0.25), cG((size_t)total, 0.125),
-        X2((size_t)total, 1.0), W((size_t)total, 0.0);
+        X2((size_t)total, 1.0), W((size_t)total, 0.0), Sv((size_t)total, 0.0);
     CheckedMem m;
     m.err = &err;
     m.total = total;
@@ -330,7 +344,7 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
         m.lo = off[u];
         m.hi = off[u] + ((int64_t)1 << lsum);
         march_dispatch<D>(B.shape, [&](auto sh) {
-            walk_block<D, OP, decltype(sh)>(B, ul, off[u], total, m, X0, X1, cG, X2, W, writes, err);
+            walk_block<D, OP, decltype(sh)>(B, ul, off[u], total, m, X0, X1, cG, X2, W, Sv, fuse, writes, err);
         });
     }
     *lds_reads_out = m.reads;
@@ -338,12 +352,14 @@ int run(int n_units, const int8_t* lv, const int64_t* off, int64_t total, int el
 }
 
 template <int D>
-int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool xorder,
+int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, bool xorder, bool fuse,
            int64_t first, int64_t stride, int64_t* nb, int64_t* reads, int32_t* writes, Err& err)
 {
-    if (op == OP_STAGE1) return run<D, OP_STAGE1>(n_units, lv, off, total, elem, xorder, first, stride, nb, reads, writes, err);
-    if (op == OP_STAGE2) return run<D, OP_STAGE2>(n_units, lv, off, total, elem, xorder, first, stride, nb, reads, writes, err);
-    return run<D, OP_REFINE>(n_units, lv, off, total, elem, xorder, first, stride, nb, reads, writes, err);
+    if (op == OP_STAGE1)
+        return run<D, OP_STAGE1>(n_units, lv, off, total, elem, xorder, fuse, first, stride, nb, reads, writes, err);
+    if (op == OP_STAGE2)
+        return run<D, OP_STAGE2>(n_units, lv, off, total, elem, xorder, fuse, first, stride, nb, reads, writes, err);
+    return run<D, OP_REFINE>(n_units, lv, off, total, elem, xorder, fuse, first, stride, nb, reads, writes, err);
 }
 
 }  // namespace
@@ -351,19 +367,20 @@ int run_op(int op, int n_units, const int8_t* lv, const int64_t* off, int64_t to
 extern "C" {
 
 // Walk entries first, first + stride, ... of the plan's marching-operator block table (every entry
-// for stride 1): the unit-by-unit table, or with xorder the XCD-grouped one.  lv: [n_units][MAXD]
+// for stride 1): the unit-by-unit table, or with xorder the XCD-grouped one; fuse: the operator also
+// solves the axis-1 lines of the units whose lines fit one tile row.  lv: [n_units][MAXD]
 // levels; off: unit offsets; writes: [total] counters (incremented).  Returns 0 when every check
 // passed, else 1 with the first failure in err.
 int march_check(int d, int op, int n_units, const int8_t* lv, const int64_t* off, int64_t total, int elem, int xorder,
-                int64_t first, int64_t stride, int64_t* n_blocks, int64_t* lds_reads, int32_t* writes, char* err,
-                int errlen)
+                int fuse, int64_t first, int64_t stride, int64_t* n_blocks, int64_t* lds_reads, int32_t* writes,
+                char* err, int errlen)
 {
     Err e;
     int rc = 2;
-    const bool xo = xorder != 0;
-    if (d == 2) rc = run_op<2>(op, n_units, lv, off, total, elem, xo, first, stride, n_blocks, lds_reads, writes, e);
-    else if (d == 3) rc = run_op<3>(op, n_units, lv, off, total, elem, xo, first, stride, n_blocks, lds_reads, writes, e);
-    else if (d == 4) rc = run_op<4>(op, n_units, lv, off, total, elem, xo, first, stride, n_blocks, lds_reads, writes, e);
+    const bool xo = xorder != 0, fz = fuse != 0;
+    if (d == 2) rc = run_op<2>(op, n_units, lv, off, total, elem, xo, fz, first, stride, n_blocks, lds_reads, writes, e);
+    else if (d == 3) rc = run_op<3>(op, n_units, lv, off, total, elem, xo, fz, first, stride, n_blocks, lds_reads, writes, e);
+    else if (d == 4) rc = run_op<4>(op, n_units, lv, off, total, elem, xo, fz, first, stride, n_blocks, lds_reads, writes, e);
     else e("d must lie in [2, 4]");
     std::snprintf(err, (size_t)errlen, "%s", e.msg.c_str());
     return e.set ? 1 : rc;

@@ -290,8 +290,10 @@ def test_schedules_agree(name):
                                   "d3_full_ragged", "d2_standard_ct", "d3_ct", "d4_ct", "long_axis0_12",
                                   "d2_standard_ct12"])
 def test_march_schedule(name, precision, tol):
-    """The plane-tiled operator (LDS ring of V planes) with the separate axis-1 solves: two steps,
-    every node of every unit against the oracle, with and without the XCD remap."""
+    """The plane-tiled operator (LDS ring of V planes), with the separate axis-1 solves and with the
+    axis-1 solve of the grids whose lines have at most 16 points fused into it (the others solved in
+    place by the axis-1 sweep): two steps, every node of every unit against the oracle, with and
+    without the XCD remap."""
     probs, grid = CASES[name]
     steps = 5
     plan = Plan(probs, grid, steps=steps, precision=precision, device=DEV)
@@ -308,14 +310,17 @@ def test_march_schedule(name, precision, tol):
         return oracle.inner_view(Yf, lv)
 
     refs = parallel(ref, items)
-    for x in (0, 1):
-        plan.set_schedule(march=1, fuse_axis0=0, resident=0, xcd_remap=x)
+    fusable = plan.schedule()["fuse_max_axis0"] <= 1024
+    for x, fz in ((0, 0), (1, 0), (0, 1), (1, 1)):
+        if fz and not fusable:
+            continue
+        plan.set_schedule(march=1, fuse_axis0=fz, resident=0, xcd_remap=x)
         plan.init()
         plan.time_step(2)
         Y = plan.state().cpu().numpy().astype(np.float64)
         for (u, sl), rr in zip(items, refs):
             err = rel_maxerr(Y[sl], rr)
-            assert err < max(tol, (4e-16 if precision == "fp64" else 2e-7) * (1 << max(u["levels"]))), (x, u, err)
+            assert err < max(tol, (4e-16 if precision == "fp64" else 2e-7) * (1 << max(u["levels"]))), (x, fz, u, err)
 
 
 def test_autotune_picks_admissible_schedule(tmp_path, monkeypatch):

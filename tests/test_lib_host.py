@@ -205,7 +205,8 @@ def test_schedule_validation():
     assert _sched(h).fuse_axis0 == 1
     assert _set(h, stencil_nodes=1, fuse_axis0=1) == L.E_INVALID
     assert _sched(h).march_available == 1
-    assert _set(h, stencil_nodes=4, fuse_axis0=1, march=1) == L.E_INVALID   # march does not fuse
+    assert _set(h, stencil_nodes=4, fuse_axis0=1, march=1) == L.OK   # short axis-1 lines in the operator
+    assert _set(h, stencil_nodes=1, fuse_axis0=1, march=1) == L.OK   # stencil_nodes does not bind march
     assert _set(h, stencil_nodes=4, fuse_axis0=0, march=2) == L.E_INVALID
     assert _set(h, stencil_nodes=4, fuse_axis0=0, march=1) == L.OK
     assert _sched(h).march == 1
@@ -231,7 +232,7 @@ def test_schedule_validation():
 
 def test_long_axis0_lines():
     """Axis-0 levels up to 16 build (the paper's standard-technique levels); the W = P solve and the
-    fused axis-0 schedule keep their 2^10 limit and say so."""
+    fused axis-0 schedules (with or without the marching operator) keep their 2^10 limit and say so."""
     p = I.paper_swaption(3)
     for grid in (I.combination(13, 1), I.combination(12, 0), I.full_grid([16, 0, 0, 0])):
         st, h = _create([p], grid, steps=16)
@@ -239,6 +240,7 @@ def test_long_axis0_lines():
         sc = _sched(h)
         assert sc.fuse_max_axis0 > 1024
         assert _set(h, stencil_nodes=8, fuse_axis0=1) == L.E_INVALID
+        assert _set(h, stencil_nodes=1, fuse_axis0=1, march=1) == L.E_INVALID   # axis-1 lines > 1024
         assert _set(h, stencil_nodes=1, fuse_axis0=0, march=1) == L.OK
         L.lib().amf_plan_destroy(h)
     gs = S.scheme_theta_gs(1.0, 1)

@@ -32,8 +32,8 @@ def harness():
     lib = C.CDLL(OUT)
     lib.march_check.restype = C.c_int
     lib.march_check.argtypes = [C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
-                                C.c_int, C.c_int64, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.c_void_p,
-                                C.c_char_p, C.c_int]
+                                C.c_int, C.c_int, C.c_int64, C.c_int64, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                C.c_void_p, C.c_char_p, C.c_int]
     return lib
 
 
@@ -65,13 +65,13 @@ def _plan_units(probs, grid, precision):
     return d, lv, off, total, elem
 
 
-def _walk(harness, probs, grid, precision, op, stride, xorder=0):
+def _walk(harness, probs, grid, precision, op, stride, xorder=0, fuse=0):
     d, lv, off, total, elem = _plan_units(probs, grid, precision)
     writes = np.zeros(total, dtype=np.int32)
     nb, reads = C.c_int64(), C.c_int64()
     err = C.create_string_buffer(512)
-    rc = harness.march_check(d, OPS[op], len(off), lv.ctypes.data, off.ctypes.data, total, elem, xorder, 0, stride,
-                             C.byref(nb), C.byref(reads), writes.ctypes.data, err, 512)
+    rc = harness.march_check(d, OPS[op], len(off), lv.ctypes.data, off.ctypes.data, total, elem, xorder, fuse, 0,
+                             stride, C.byref(nb), C.byref(reads), writes.ctypes.data, err, 512)
     assert rc == 0, err.value.decode()
     inner = np.zeros(total, dtype=bool)
     for u in range(len(off)):
@@ -100,21 +100,22 @@ SMALL = {
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", list(SMALL))
 def test_march_small_plans_every_block(harness, name, precision, op):
-    """The unit-by-unit table and the XCD-grouped one."""
+    """The unit-by-unit table and the XCD-grouped one, with and without the fused axis-1 solve."""
     probs, grid = SMALL[name]
-    _walk(harness, probs, grid, precision, op, 1, 0)
-    _walk(harness, probs, grid, precision, op, 1, 1)
+    for fuse in (0, 1):
+        _walk(harness, probs, grid, precision, op, 1, 0, fuse)
+        _walk(harness, probs, grid, precision, op, 1, 1, fuse)
 
 
-@pytest.mark.parametrize("xorder", [0, 1])
-@pytest.mark.parametrize("op", ["stage1", "stage2"])
+@pytest.mark.parametrize("xorder,fuse", [(0, 0), (1, 0), (1, 1)])
+@pytest.mark.parametrize("op", ["stage1", "stage2", "refine"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_march_benchmark_plan(harness, precision, op, xorder):
-    """The d = 4, n = 7, psi = 3 workload (295 grids, 94.6M nodes).  The refinement takes stage 1's
-    pipeline (stage values one plane ahead) and differs only in which vectors it reads."""
+def test_march_benchmark_plan(harness, precision, op, xorder, fuse):
+    """The d = 4, n = 7, psi = 3 workload (295 grids, 94.6M nodes), in the benchmark's XCD order
+    with and without the fused axis-1 solve."""
     w = I.workload_ct4()
     stride = 1 if os.environ.get("AMF_MARCH_FULL") == "1" else 13
-    nb, reads = _walk(harness, w["problems"], w["grid"], precision, op, stride, xorder)
+    nb, reads = _walk(harness, w["problems"], w["grid"], precision, op, stride, xorder, fuse)
     assert nb > 10000
 
 
@@ -123,3 +124,4 @@ def test_march_batch_plan_sample(harness):
     per axis, tiles smaller than a block)."""
     w = I.workload_batch4(count=16)
     _walk(harness, w["problems"], w["grid"], "fp32", "stage2", 1)
+    _walk(harness, w["problems"], w["grid"], "fp32", "refine", 1, 1, 1)
