@@ -177,7 +177,10 @@ def run_form(torch, Plan, w, precision, steps, warmup, tune=True, prof_solves=2)
     achieved = ks["algo_bytes"] / (ks["ms"] * 1e-3) / 1e9 if ks["ms"] > 0 else 0.0
     launches = max(ks["launches"], 1)
     from paper_2408_00559_amd import _lib as L
-    roof = {"kernel": dom, "kernel_symbol": L.K_SYMBOLS[dom], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+    sym = L.K_SYMBOLS[dom]
+    if plan.schedule()["march"] and dom in ("stage1", "stage2", "refine"):   # the plane-tiled operator ran
+        sym = "k_march<%s>" % {"stage1": "OP_STAGE1", "stage2": "OP_STAGE2", "refine": "OP_REFINE"}[dom]
+    roof = {"kernel": dom, "kernel_symbol": sym, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_for(dom, precision),
             "algo_bytes_per_launch": ks["algo_bytes"] / launches,
             "avg_launch_us": ks["ms"] * 1e3 / launches, "launches_per_solve": ks["launches"] / prof_solves,

@@ -143,7 +143,8 @@ def test_dirichlet_one_step(name):
 
 
 @pytest.mark.parametrize("schedule", [dict(stencil_nodes=2, fuse_axis0=1), dict(stencil_nodes=2, xcd_remap=2),
-                                      dict(stencil_nodes=1, xcd_remap=1), dict(resident=1)])
+                                      dict(stencil_nodes=1, xcd_remap=1), dict(resident=1),
+                                      dict(march=1, fuse_axis0=0, xcd_remap=1), dict(march=1, fuse_axis0=1, xcd_remap=1)])
 def test_dirichlet_schedules(schedule):
     probs, grid = CASES["d4_ct_mixed"]
     plan = Plan(probs, grid, steps=4, device=DEV)
@@ -191,12 +192,14 @@ def test_generic_stages_one_step(name, s, seed):
                     nsteps=2)
 
 
+@pytest.mark.parametrize("schedule", [dict(stencil_nodes=2, fuse_axis0=1, march=0),
+                                      dict(march=1, fuse_axis0=1, xcd_remap=1)])
 @pytest.mark.parametrize("s,seed", [(3, 0), (3, 5)])
-def test_generic_stages_fused_schedule(s, seed):
+def test_generic_stages_fused_schedule(s, seed, schedule):
     probs, grid = CASES["d4_ct_mixed"]
     a, q, b = _table(s, seed)
     _one_step_check(probs, grid, S.scheme_generic(a, q, b, 0.6, 0.6), oracle.scheme_generic(a, q, b, 0.6, 0.6),
-                    nsteps=2, schedule=dict(stencil_nodes=2, fuse_axis0=1))
+                    nsteps=2, schedule=schedule)
 
 
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 1e-5)])
