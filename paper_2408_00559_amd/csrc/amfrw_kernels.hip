@@ -1484,83 +1484,149 @@ __device__ __forceinline__ int res_at(const ResGeom<D>& G, int n)
     return (n & (G.M[0] - 1)) + (n >> G.L[0]) * G.P0;
 }
 
-// Zero-face Sketch-1 operator on LDS vectors, fused with the stage combination OP, one node per
-// thread and iteration.  Lower-face neighbours are 0 and the upper-face ghost is the node below the
-// face (eq. bound1); a neighbour beyond a face is read at the node itself (an index inside the unit)
-// and replaced by a select, and the mixed and advection coefficients vanish on the upper faces.
-template <typename T, int D, int OP>
-__device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const T* st, const T* cst, int dirichlet, T sc,
-                                            T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
+// Zero-face Sketch-1 operator on LDS vectors, fused with the stage combination OP.  A thread takes
+// R consecutive nodes of one axis-1 row (R divides M_1), so every neighbour row is read as a short
+// segment at fixed offsets from one address, and the face tests, coefficient products and masks of
+// the other axes are formed once for the R nodes.  Lower-face neighbours are 0 and the upper-face
+// ghost is the node below the face (eq. bound1); a neighbour beyond a face is read at an index
+// inside the unit and replaced by 0 (a 0/1 mask) or by the ghost, and the mixed and advection
+// coefficients vanish on the upper faces.
+template <typename T, int D, int OP, int R>
+__device__ __forceinline__ void res_stencil_r(const ResGeom<D>& G, const T* st, const T* cst, int dirichlet, T sc,
+                                              T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
 {
+    constexpr int NA = D - 1;                     // axes other than axis 1 (0-based 1 .. D-1)
     const T* tv = st + G.tb[D - 1];
+    const T* t0 = st + G.tb[0];
     const T tdV = tv[G.MV], tmixV = tv[G.MV + 1];
-    for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) {
-        int j[D];                                 // 0-based node indices
+    const int ng = G.Pn / R;
+    auto X = [&](int idx) -> T {
+        if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
+        else return X0[idx];
+    };
+    for (int g = threadIdx.x; g < ng; g += RES_BLOCK) {
+        const int n = g * R;                      // first node of the group
+        const int j0 = n & (G.M[0] - 1);
+        const bool lo0 = j0 == 0, hi0 = j0 + R == G.M[0];
+        int j[D], dm[D], dp[D];
         bool lo[D], hi[D];
-        int dm[D], dp[D];                         // offsets of the lower / upper neighbours (0 beyond a face)
+        T mk[D];                                  // 0 on the lower face of the axis, else 1
+        bool face = false;                        // Dirichlet faces of the rate axes 2..N-1 (axis 1: per node)
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
+        for (int i = 1; i < D; ++i) {
             j[i] = (n >> G.N[i]) & (G.M[i] - 1);
             lo[i] = j[i] == 0;
             hi[i] = j[i] == G.M[i] - 1;
             dm[i] = lo[i] ? 0 : G.S[i];
             dp[i] = hi[i] ? 0 : G.S[i];
+            mk[i] = lo[i] ? T(0) : T(1);
+            if (i < D - 1) face |= dir_face(dirichlet, j[i] + 1, G.M[i]);
         }
         const int at = res_at<D>(G, n);
-        auto X = [&](int idx) -> T {
-            if constexpr (OP == OP_STAGE2) return X0[idx] + av * X1[idx];
-            else return X0[idx];
+        // a row segment: positions j0 - 1 .. j0 + R of the row through `base` (the edges clamped to
+        // the row: 0 below the lower face, the ghost j0 + R - 2 beyond the upper face)
+        auto seg = [&](int base, T (&v)[R + 2]) {
+#pragma unroll
+            for (int q = 1; q <= R; ++q) v[q] = X(base + q - 1);
+            const T l = X(base - (lo0 ? 0 : 1)), h = X(base + R - (hi0 ? 1 : 0));
+            v[0] = lo0 ? T(0) : l;
+            v[R + 1] = hi0 ? v[R - 1] : h;
         };
-        const T c0 = X(at);
-        T xm[D], xp[D], tmix[D], tphi[D];
+        T c[R + 2];
+        seg(at, c);
+        T acc[R];
+        // coefficients of axis 1 per node, of the other axes per group
+        T td0[R], tm0[R];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const T a = X(at - dm[i]);
-            const T b = X(at + dp[i]);
-            xm[i] = lo[i] ? T(0) : a;
-            xp[i] = hi[i] ? xm[i] : b;
+        for (int q = 0; q < R; ++q) {
+            td0[q] = t0[j0 + q];
+            tm0[q] = t0[G.M[0] + j0 + q];
+            acc[q] = td0[q] * (c[q + 2] - T(2) * c[q + 1] + c[q]);
         }
-        const T vsq = tv[j[D - 1]];
-        T acc = tdV * (xp[D - 1] - T(2) * c0 + xm[D - 1]);
-        tmix[D - 1] = tmixV;
-        tphi[D - 1] = T(0);
+        T tmix[D], tphi[D];
+        tmix[0] = T(0);
+        tphi[0] = T(0);
 #pragma unroll
-        for (int i = 0; i < D - 1; ++i) {
-            const T* ti = st + G.tb[i];
-            tmix[i] = ti[G.M[i] + j[i]];
-            tphi[i] = ti[2 * G.M[i] + j[i]];
-            acc += ti[j[i]] * (xp[i] - T(2) * c0 + xm[i]);
-        }
+        for (int i = 1; i < D; ++i) {
+            T m[R + 2], p[R + 2];
+            seg(at - dm[i], m);
+            seg(at + dp[i], p);
 #pragma unroll
-        for (int i = 0; i < D - 1; ++i) {
+            for (int q = 0; q < R + 2; ++q) m[q] *= mk[i];          // the row below the lower face is 0
+            T tdi;
+            if (i < D - 1) {
+                const T* ti = st + G.tb[i];
+                tdi = ti[j[i]];
+                tmix[i] = ti[G.M[i] + j[i]];
+                tphi[i] = ti[2 * G.M[i] + j[i]];
+            } else {
+                tdi = tdV;
+                tmix[i] = tmixV;
+                tphi[i] = T(0);
+            }
+            // pair (axis 1, axis i): zero on either upper face
+            const T c0i = (i < D - 1) ? cst[CST_RHO + 0 * MAXD + i] : cst[CST_SPHI + 0];
+            const T c0t = hi[i] ? T(0) : c0i * tmix[i];
 #pragma unroll
-            for (int k = i + 1; k < D; ++k) {
-                const T pp = X(at + dp[i] + dp[k]);
-                const T mm = X(at - dm[i] - dm[k]);
-                const T pm = X(at + dp[i] - dm[k]);
-                const T mp = X(at - dm[i] + dp[k]);
-                const T xx = pp + ((lo[i] || lo[k]) ? T(0) : mm) - (lo[k] ? T(0) : pm) - (lo[i] ? T(0) : mp);
-                const T cik = (k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i];
-                const T cf = (hi[i] || hi[k]) ? T(0) : cik * tmix[i] * tmix[k];
-                acc += cf * xx;
+            for (int q = 0; q < R; ++q) {
+                const T xm = m[q + 1];
+                const T xp = hi[i] ? xm : p[q + 1];
+                acc[q] += tdi * (xp - T(2) * c[q + 1] + xm);
+                const bool h0 = hi0 && q == R - 1;
+                const T cf = h0 ? T(0) : tm0[q] * c0t;
+                acc[q] += cf * (p[q + 2] + m[q] - m[q + 2] - p[q]);
+            }
+            if (i < D - 1) {                       // advection of the rate axes 2..N-1
+                T sacc = T(0);
+#pragma unroll
+                for (int jj = 1; jj <= i; ++jj) sacc += cst[CST_RHO + i * MAXD + jj] * tphi[jj];
+                const T ca = hi[i] ? T(0) : tmix[i] * sacc;
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const T xm = m[q + 1];
+                    const T xp = hi[i] ? xm : p[q + 1];
+                    acc[q] += ca * (xp - xm);
+                }
             }
         }
+        // pairs (i, k) of the other axes: corner segments of R nodes
 #pragma unroll
         for (int i = 1; i < D - 1; ++i) {
-            T sacc = T(0);
 #pragma unroll
-            for (int jj = 1; jj <= i; ++jj) sacc += cst[CST_RHO + i * MAXD + jj] * tphi[jj];
-            const T ca = hi[i] ? T(0) : tmix[i] * sacc;
-            acc += ca * (xp[i] - xm[i]);
+            for (int k = i + 1; k < D; ++k) {
+                const T cik = (k < D - 1) ? cst[CST_RHO + i * MAXD + k] : cst[CST_SPHI + i];
+                const T cf = (hi[i] || hi[k]) ? T(0) : cik * tmix[i] * tmix[k];
+                const int bpp = at + dp[i] + dp[k], bmm = at - dm[i] - dm[k];
+                const int bpm = at + dp[i] - dm[k], bmp = at - dm[i] + dp[k];
+                const T mmm = mk[i] * mk[k];
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const T xx = X(bpp + q) + mmm * X(bmm + q) - mk[k] * X(bpm + q) - mk[i] * X(bmp + q);
+                    acc[q] += cf * xx;
+                }
+            }
         }
-        bool face = false;                       // Dirichlet rate faces: null rows
+        const T vsq = tv[j[D - 1]];
 #pragma unroll
-        for (int i = 0; i < D - 1; ++i) face |= dir_face(dirichlet, j[i] + 1, G.M[i]);
-        const T F = face ? T(0) : vsq * acc;
-        if constexpr (OP == OP_STAGE1) Wout[at] = sc * (F + cGg[n]);
-        else if constexpr (OP == OP_STAGE2) Wout[at] = sc * (F + cGg[n]) + qv * X1[at];
-        else Wout[at] = T(2) * Wout[at] - c0 + sc * F;
+        for (int q = 0; q < R; ++q) {
+            const bool fq = face || dir_face(dirichlet, j0 + q + 1, G.M[0]);
+            const T F = fq ? T(0) : vsq * acc[q];
+            const int aq = at + q;
+            if constexpr (OP == OP_STAGE1) Wout[aq] = sc * (F + cGg[n + q]);
+            else if constexpr (OP == OP_STAGE2) Wout[aq] = sc * (F + cGg[n + q]) + qv * X1[aq];
+            else Wout[aq] = T(2) * Wout[aq] - c[q + 1] + sc * F;
+        }
     }
+}
+
+template <typename T, int D, int OP>
+__device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const T* st, const T* cst, int dirichlet, T sc,
+                                            T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
+{
+    // two nodes per thread wherever a row allows it (four take so many registers that occupancy
+    // halves: measured slower)
+    if (G.M[0] >= 2) res_stencil_r<T, D, OP, 2>(G, st, cst, dirichlet, sc, av, qv, X0, X1, Wout, cGg);
+    else res_stencil_r<T, D, OP, 1>(G, st, cst, dirichlet, sc, av, qv, X0, X1, Wout, cGg);
 }
 
 // Solves along one axis of a resident unit (LDS `in` -> LDS `io`, in place when they coincide):
@@ -1612,7 +1678,7 @@ __device__ __forceinline__ void res_chain(const ResGeom<D>& G, const T* const (&
 }
 
 template <typename T, int D>
-__global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
+__device__ __forceinline__ void resident_unit(const DevPlan& P, const ResArgs& A)
 {
     extern __shared__ __align__(16) unsigned char res_smem[];
     const UnitDev U = P.units[blockIdx.x];
@@ -1679,6 +1745,20 @@ __global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
         res_chain<T, D>(G, fa, sA, sB, true, sW, sK, b1, b2);
     }
     for (int n = threadIdx.x; n < G.Pn; n += RES_BLOCK) Wg[n] = sW[res_at<D>(G, n)];
+}
+
+template <typename T, int D>
+__global__ __launch_bounds__(RES_BLOCK) void k_resident(DevPlan P, ResArgs A)
+{
+    resident_unit<T, D>(P, A);
+}
+
+// The same kernel held to 128 registers (four wavefronts per SIMD): FP32 with d <= 4 spills a few
+// registers and runs faster at the higher occupancy; larger d and FP64 would spill far more.
+template <typename T, int D>
+__global__ __launch_bounds__(RES_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_resident_w4(DevPlan P, ResArgs A)
+{
+    resident_unit<T, D>(P, A);
 }
 
 template <typename T>
@@ -2178,8 +2258,14 @@ static hipError_t resident_t(const DevPlan& P, const ResArgs& a, hipStream_t s)
     const size_t shm = ((size_t)4 * a.lds_len + (size_t)a.tab_len) * sizeof(T);
     switch (P.d) {
     case 2: hipLaunchKernelGGL((k_resident<T, 2>), g, b, shm, s, P, a); break;
-    case 3: hipLaunchKernelGGL((k_resident<T, 3>), g, b, shm, s, P, a); break;
-    case 4: hipLaunchKernelGGL((k_resident<T, 4>), g, b, shm, s, P, a); break;
+    case 3:
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_resident_w4<T, 3>), g, b, shm, s, P, a);
+        else hipLaunchKernelGGL((k_resident<T, 3>), g, b, shm, s, P, a);
+        break;
+    case 4:
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((k_resident_w4<T, 4>), g, b, shm, s, P, a);
+        else hipLaunchKernelGGL((k_resident<T, 4>), g, b, shm, s, P, a);
+        break;
     case 5: hipLaunchKernelGGL((k_resident<T, 5>), g, b, shm, s, P, a); break;
     case 6: hipLaunchKernelGGL((k_resident<T, 6>), g, b, shm, s, P, a); break;
     default: return hipErrorInvalidValue;
