@@ -1623,9 +1623,9 @@ template <typename T, int D, int OP>
 __device__ __forceinline__ void res_stencil(const ResGeom<D>& G, const T* st, const T* cst, int dirichlet, T sc,
                                             T av, T qv, const T* X0, const T* X1, T* Wout, const T* cGg)
 {
-    // two nodes per thread wherever a row allows it (four take so many registers that occupancy
-    // halves: measured slower)
-    if (G.M[0] >= 2) res_stencil_r<T, D, OP, 2>(G, st, cst, dirichlet, sc, av, qv, X0, X1, Wout, cGg);
+    // two nodes per thread wherever a row allows it, for d <= 4 (four, or two at d >= 5, take so many
+    // registers that occupancy halves)
+    if (D <= 4 && G.M[0] >= 2) res_stencil_r<T, D, OP, 2>(G, st, cst, dirichlet, sc, av, qv, X0, X1, Wout, cGg);
     else res_stencil_r<T, D, OP, 1>(G, st, cst, dirichlet, sc, av, qv, X0, X1, Wout, cGg);
 }
 
