@@ -404,7 +404,8 @@ def run_ct6(torch, Plan):
 def run_surrogate(torch, Plan):
     """Form (4) next to the solver on the surrogate's label discretisation (d = 6, n = 5, psi = 1,
     100 steps, FP32 with FP64 combine): solver prices/s on 512 seeded requests, the BF16-MFMA
-    network's prices/s on 50,000 requests (throughput does not depend on the weights), and the
+    network's inference prices/s (amf_mlp_infer) on 50,000 and on 2^21 requests (throughput does not
+    depend on the weights), and the
     held-out accuracy and fallback rates of the trained network as recorded in
     profiles/surrogate_d6_n5.json by train_surrogate."""
     from paper_2408_00559_amd import autotune
@@ -426,15 +427,26 @@ def run_surrogate(torch, Plan):
     net = S.Mlp(n_in=8, width=256, depth=3, max_batch=50000, seed=1)
     x = torch.randn(50000, 8, dtype=torch.float32, device="cuda:0")
     net.set_normalization([0.0] * 8, [1.0] * 8, 0.02, 0.01)
-    net.forward(x)
+    net.infer(x)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(10):
-        net.forward(x)
+        net.infer(x)
     torch.cuda.synchronize()
     net_rate = 10 * 50000 / (time.perf_counter() - t0)
+    xl = torch.randn(1 << 21, 8, dtype=torch.float32, device="cuda:0")   # a large batch: MFMA-bound
+    net.infer(xl)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        net.infer(xl)
+    torch.cuda.synchronize()
+    net_rate_large = 5 * xl.shape[0] / (time.perf_counter() - t0)
+    del xl
     res = {"workload": "surrogate labels d6 n5 psi1 100 steps", "solver_prices_per_s": solver_rate,
-           "network_prices_per_s": net_rate, "network_flop_per_price": 2 * (8 * 256 + 2 * 256 * 256 + 256 * 2)}
+           "network_prices_per_s": net_rate, "network_prices_per_s_2M_batch": net_rate_large,
+           "network_flop_per_price": 2 * (8 * 256 + 2 * 256 * 256 + 256 * 2),
+           "network_padded_mfma_tflops_2M_batch": net_rate_large * 2 * (32 * 256 + 2 * 256 * 256 + 256 * 32) / 1e12}
     rep_path = os.path.join(ROOT, "profiles", "surrogate_d6_n5.json")
     if os.path.exists(rep_path):
         rep = json.load(open(rep_path))

@@ -340,6 +340,11 @@ amf_status amf_mlp_grads(amf_mlp* mlp, float* d_grads, void* stream);
 /* d_x: [batch, n_in] raw features (FP32, device).  d_out: [batch, 2] = (price, estimated relative
  * error of the price). */
 amf_status amf_mlp_forward(amf_mlp* mlp, const float* d_x, int32_t batch, float* d_out, void* stream);
+/* Inference only: the same outputs as amf_mlp_forward (same rounding points and accumulation order),
+ * any batch >= 1, nothing kept for a backward pass.  Networks whose layers are at most 256 wide run
+ * as one launch in which each workgroup takes 64 requests through every layer with the activations
+ * in LDS; wider ones fall back to the training forward pass in chunks of max_batch. */
+amf_status amf_mlp_infer(amf_mlp* mlp, const float* d_x, int32_t batch, float* d_out, void* stream);
 /* After amf_mlp_forward of the same batch: gradient of sum_b dy[b] . y[b] with respect to the
  * parameters, y the two raw network outputs; d_dy is [batch, 2] FP32. */
 amf_status amf_mlp_backward(amf_mlp* mlp, const float* d_dy, int32_t batch, void* stream);

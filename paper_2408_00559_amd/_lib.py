@@ -160,6 +160,6 @@ EXPORTED = ["amf_abi_version", "amf_last_error", "amf_scheme_amfrw2", "amf_schem
             "amf_state_read", "amf_apply_operator",
             "amf_axis_solve", "amf_schedule_get", "amf_schedule_set", "amf_profile_begin", "amf_profile_end", "amf_plan_destroy",
             "amf_mlp_last_error", "amf_mlp_create", "amf_mlp_info_get", "amf_mlp_bind",
-            "amf_mlp_set_normalization", "amf_mlp_params", "amf_mlp_grads", "amf_mlp_forward",
+            "amf_mlp_set_normalization", "amf_mlp_params", "amf_mlp_grads", "amf_mlp_forward", "amf_mlp_infer",
             "amf_mlp_backward", "amf_mlp_train_step", "amf_mlp_destroy", "amf_mlp_set_router",
             "amf_price_or_fallback", "amf_solve_static"]

@@ -148,6 +148,106 @@ __global__ void k_output(const float* Y, int batch, int ldy, const float* omean,
     out[2 * b + 1] = lg ? e : e / fmaxf(fabsf(price), 1e-30f);
 }
 
+// Inference (no activations kept for a backward pass): one workgroup of four wavefronts takes
+// INF_ROWS requests through every layer.  The layer input sits in LDS as BF16 rows; each wavefront
+// computes the 16 x 16 output tiles of its columns (tiles w, w + 4, ... of the layer) for all rows,
+// with the weights read as MFMA B operands from global memory (they stay in L2: every workgroup
+// reads the same ones); bias and SiLU are applied in the epilogue and the BF16 result goes to the
+// other LDS buffer.  Rounding points and accumulation order equal those of the training forward
+// pass (k_input, k_gemm_nt, k_output), so the outputs are the same.
+constexpr int INF_ROWS = 64;                 // requests per workgroup (4 row tiles)
+constexpr int INF_MAXW = 256;                // widest layer input or output
+constexpr int INF_LD = INF_MAXW + 8;         // LDS row pitch (BF16 elements): rows 4 banks apart
+
+struct InferLayer {
+    const __bf16* W;   // [N, K] row-major
+    const float* b;    // [N]
+    int N, K;
+};
+struct InferArgs {
+    const float* x;
+    int batch, nin, kin, nl;
+    const float* mean;
+    const float* stdv;
+    const float* omean;
+    const float* ostd;
+    float* out;        // [batch, 2]
+    InferLayer L[MAX_LAYERS];
+};
+
+__global__ __launch_bounds__(256) void k_mlp_infer(InferArgs A)
+{
+    __shared__ __align__(16) __bf16 buf[2][INF_ROWS * INF_LD];
+    __shared__ float yout[INF_ROWS][2];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int row0 = blockIdx.x * INF_ROWS;
+    // inputs, normalised and zero-padded to kin columns (rows past the batch are zero)
+    for (int i = tid; i < INF_ROWS * A.kin; i += 256) {
+        const int r = i / A.kin, c = i % A.kin, b = row0 + r;
+        float v = 0.0f;
+        if (b < A.batch && c < A.nin) v = (A.x[(size_t)b * A.nin + c] - A.mean[c]) / A.stdv[c];
+        buf[0][r * INF_LD + c] = f2bf(v);
+    }
+    __syncthreads();
+    const int r = lane & 15, kb = lane >> 4;
+    for (int l = 0; l < A.nl; ++l) {
+        const InferLayer Ly = A.L[l];
+        const __bf16* in = buf[l & 1];
+        __bf16* outb = buf[(l + 1) & 1];
+        const bool last = l == A.nl - 1;
+        const int tn = Ly.N / TILE;
+        for (int ct0 = wave; ct0 < tn; ct0 += 16) {           // up to four column tiles per pass
+            f32x4 acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int k = 0; k < Ly.K; k += KSTEP) {
+                bf16x8 a[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = *(const bf16x8*)(in + (i * TILE + r) * INF_LD + k + kb * 8);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ct = ct0 + 4 * j;
+                    if (ct < tn) {
+                        const bf16x8 bv = *(const bf16x8*)(Ly.W + (size_t)(ct * TILE + r) * Ly.K + k + kb * 8);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bv, acc[i][j], 0, 0, 0);
+                    }
+                }
+            }
+            // lane holds C[i*16 + 4*(lane/16) + e][ct*16 + lane%16], e = 0..3
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int ct = ct0 + 4 * j;
+                if (ct >= tn) continue;
+                const int n = ct * TILE + (lane & 15);
+                const float bn = Ly.b[n];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int m = i * TILE + 4 * (lane >> 4) + e;
+                        const float v = acc[i][j][e] + bn;
+                        if (!last) outb[m * INF_LD + n] = f2bf(v * sigmoidf_(v));
+                        else if (n < 2) yout[m][n] = v;
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    // outputs as k_output
+    if (tid < INF_ROWS && row0 + tid < A.batch) {
+        const int b = row0 + tid;
+        const bool lg = A.omean[8] != 0.0f;
+        const float u = yout[tid][0] * A.ostd[0] + A.omean[0];
+        const float price = lg ? __expf(u) : u;
+        const float e = __expf(yout[tid][1]) * A.ostd[0];
+        A.out[2 * b + 0] = price;
+        A.out[2 * b + 1] = lg ? e : e / fmaxf(fabsf(price), 1e-30f);
+    }
+}
+
 // Router of the price_or_fallback call: request b is served by the network when its features lie in
 // the training box [lo, hi], its price p is finite and its calibrated error estimate e = calib est
 // satisfies e <= tol or e |p| <= abs_floor; used[b] = 1 routes it to the solver.
@@ -627,6 +727,40 @@ amf_status amf_mlp_forward(amf_mlp* N, const float* d_x, int32_t batch, float* d
     return hipchk(hipGetLastError(), "output");
 }
 
+amf_status amf_mlp_infer(amf_mlp* N, const float* d_x, int32_t batch, float* d_out, void* stream)
+{
+    if (!N || !N->ws || !d_x || !d_out) return mfail(AMF_E_INVALID, "null argument");
+    if (batch < 1) return mfail(AMF_E_INVALID, "batch must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    bool fits = N->nl <= MAX_LAYERS && N->L[0].K <= INF_MAXW && N->L[N->nl - 1].N >= 2;
+    for (int l = 0; l < N->nl; ++l) fits = fits && N->L[l].N <= INF_MAXW && N->L[l].K <= INF_MAXW;
+    if (!fits) {                                  // wider networks: the training forward pass, in chunks
+        for (int c0 = 0; c0 < batch; c0 += N->max_batch) {
+            const int b = std::min(N->max_batch, batch - c0);
+            amf_status st = amf_mlp_forward(N, d_x + (size_t)c0 * N->n_in, b, d_out + 2 * (size_t)c0, stream);
+            if (st) return st;
+        }
+        return AMF_OK;
+    }
+    InferArgs a{};
+    a.x = d_x;
+    a.batch = batch;
+    a.nin = N->n_in;
+    a.kin = N->L[0].K;
+    a.nl = N->nl;
+    const float* norm = N->at<float>(N->o_norm);
+    a.mean = norm;
+    a.stdv = norm + 16;
+    a.omean = norm + 32;
+    a.ostd = norm + 48;
+    a.out = d_out;
+    const __bf16* wbf = N->at<__bf16>(N->o_wbf);
+    const float* p = N->at<float>(N->o_p);
+    for (int l = 0; l < N->nl; ++l) a.L[l] = InferLayer{wbf + N->L[l].wb, p + N->L[l].b, N->L[l].N, N->L[l].K};
+    hipLaunchKernelGGL(k_mlp_infer, dim3((unsigned)((batch + INF_ROWS - 1) / INF_ROWS)), dim3(256), 0, s, a);
+    return hipchk(hipGetLastError(), "infer");
+}
+
 amf_status amf_mlp_set_router(amf_mlp* N, const float* box_lo, const float* box_hi, float calib)
 {
     if (!N || !N->ws || !box_lo || !box_hi) return mfail(AMF_E_INVALID, "null argument");
@@ -706,7 +840,7 @@ amf_status mlp_route(amf_mlp* N, const float* d_x, int64_t n, float tol, float a
     float* out = (float*)(N->ws + N->o_route);
     for (int64_t c0 = 0; c0 < n; c0 += N->max_batch) {
         const int b = (int)std::min<int64_t>(N->max_batch, n - c0);
-        amf_status st = amf_mlp_forward(N, d_x + c0 * N->n_in, b, out, s);
+        amf_status st = amf_mlp_infer(N, d_x + c0 * N->n_in, b, out, s);
         if (st) return st;
         hipLaunchKernelGGL(k_route, dim3((b + 255) / 256), dim3(256), 0, s, out, d_x + c0 * N->n_in, b, N->n_in,
                            (const float*)(N->ws + N->o_box), N->calib, tol, abs_floor, d_prices + c0, d_used + c0);

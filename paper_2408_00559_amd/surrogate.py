@@ -42,6 +42,8 @@ def _mlp_lib():
         lib.amf_mlp_grads.argtypes = [vp, vp, vp]
         lib.amf_mlp_forward.restype = st
         lib.amf_mlp_forward.argtypes = [vp, vp, C.c_int32, vp, vp]
+        lib.amf_mlp_infer.restype = st
+        lib.amf_mlp_infer.argtypes = [vp, vp, C.c_int32, vp, vp]
         lib.amf_mlp_backward.restype = st
         lib.amf_mlp_backward.argtypes = [vp, vp, C.c_int32, vp]
         lib.amf_mlp_train_step.restype = st
@@ -145,6 +147,14 @@ class Mlp:
             e = min(B, s + self.max_batch)
             _check(_mlp_lib().amf_mlp_forward(self._h, C.c_void_p(x[s:e].data_ptr()), e - s,
                                               C.c_void_p(out[s:e].data_ptr()), _stream()))
+        return out
+
+    def infer(self, x: torch.Tensor) -> torch.Tensor:
+        """Inference only (amf_mlp_infer): the outputs of forward, nothing kept for backward."""
+        x = x.to(device=self.device, dtype=torch.float32).contiguous()
+        out = torch.empty(x.shape[0], 2, dtype=torch.float32, device=self.device)
+        _check(_mlp_lib().amf_mlp_infer(self._h, C.c_void_p(x.data_ptr()), x.shape[0], C.c_void_p(out.data_ptr()),
+                                        _stream()))
         return out
 
     def backward(self, dy: torch.Tensor):

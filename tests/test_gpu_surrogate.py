@@ -49,6 +49,25 @@ def test_forward_log_target_matches_reference():
     assert np.max(np.abs(np.log(out[:, 1]) - np.log(err))) < 2e-2
 
 
+@pytest.mark.parametrize("out_log", [False, True])
+def test_infer_matches_forward_and_reference(out_log):
+    """amf_mlp_infer (one launch, activations in LDS, any batch) gives the outputs of the training
+    forward pass: the same BF16 rounding points and MFMA accumulation order, so equal to FP32
+    rounding; a batch above max_batch and not a multiple of the 64-request workgroup; and it matches
+    the FP64 reference as the forward pass does."""
+    net, lay, x, mean, std = _setup(seed=6, B=2500)
+    if out_log:
+        net.set_normalization(mean, std, -4.0, 0.5, out_log=True)
+    xt = torch.tensor(x)
+    fwd = torch.cat([net.forward(xt[i:i + 1000]) for i in range(0, 2500, 1000)]).cpu().numpy()
+    inf = net.infer(xt).cpu().numpy()
+    assert np.max(np.abs(inf - fwd) / np.maximum(np.abs(fwd), 1e-30)) < 1e-6
+    p = net.params().cpu().numpy().astype(np.float64)
+    y, _ = M.forward(lay, p, x[:300], mean, std, bf16=True)
+    price = np.exp(y[:, 0] * 0.5 - 4.0) if out_log else y[:, 0] * 0.01 + 0.02
+    assert np.max(np.abs(inf[:300, 0] - price)) < 2e-3 * np.max(np.abs(price))
+
+
 def test_gradients_match_reference():
     net, lay, x, mean, std = _setup(seed=5, B=96)
     rng = np.random.default_rng(7)
