@@ -4,7 +4,7 @@ barriers, and every inner node written exactly once.  CPU only; the plans come f
 own host code (amf_plan_create needs no GPU).
 
 The d = 4 benchmark plans (295 grids, 94.6M nodes) are walked in full when AMF_MARCH_FULL=1 (a few
-minutes); by default every 7th block of them, and every block of the smaller plans."""
+minutes); by default every 13th block of them, and every block of the smaller plans."""
 import ctypes as C
 import os
 import subprocess
