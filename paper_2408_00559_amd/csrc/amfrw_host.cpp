@@ -663,7 +663,8 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                         int kb = ka;
                         while (kb < k1 && unit_vec_ok(ord[kb]) == ok) ++kb;
                         const int v = ok ? vw : 1;
-                        const int per = LINE_BLOCK * v;
+                        const int slots = lm <= PAIR_LM && ax < d - 1 ? 2 : 1;   // the update runs on axis d - 1
+                        const int per = LINE_BLOCK * v * slots;
                         int k = ka;
                         for (int64_t s = lo[ka]; s < lo[kb]; s += per) {
                             while (s >= lo[k + 1]) ++k;
@@ -673,6 +674,7 @@ amf_status amf_plan_create(const amf_problem* probs, int32_t n_probs, const amf_
                             B.k_start = k;
                             B.lm = lm;
                             B.vec = v;
+                            B.slots = slots;
                             P->ax_blk[ax].push_back(B);
                         }
                         ka = kb;

@@ -13,6 +13,7 @@ namespace amf {
 constexpr int NODE_BLOCK = 256;    // threads per block of the per-node kernels
 constexpr int WAVE = 64;           // lanes of a wavefront
 constexpr int LINE_BLOCK = 256;    // threads per block of the sweep kernels
+constexpr int PAIR_LM = 2;         // short strided lines of at most 2^PAIR_LM points: two line slots per thread
 constexpr int UNIT_ALIGN = 64;     // unit offsets are multiples of 64 elements
 constexpr int SEG = 16;            // rows per lane in the partitioned solve of long contiguous lines
 // Longer strided lines: seg_rows consecutive rows per thread (one line: 8 in FP64, 32 in FP32;
@@ -81,14 +82,16 @@ __host__ __device__ __forceinline__ bool dir_face(int dirichlet, int j, int M) {
 
 // A block of the sweep along one axis: lines [line_start, line_end) of the axis' line list, all
 // of length 2^lm; k_start indexes the axis' unit list at line_start; vec: adjacent lines per
-// thread of the short-line sweep (1, or 16 B / element when all the block's units allow it).
+// thread of the short-line sweep (1, or 16 B / element when all the block's units allow it);
+// slots: line slots per thread of the short-line sweep (2 for lines of at most 2^PAIR_LM points on
+// the axes 2..N-1, the second LINE_BLOCK slots after the first; else 1).
 struct alignas(16) SweepBlk {
     int64_t line_start;
     int64_t line_end;
     int32_t k_start;
     int32_t lm;
     int32_t vec;
-    int32_t pad_;
+    int32_t slots;
 };
 
 // A block of the streaming operator with R consecutive axis-1 nodes per thread, over one run of

@@ -899,8 +899,73 @@ __device__ __forceinline__ void sweep_strided_regv(const DevPlan& P, const Sweep
     }
 }
 
+template <typename T, int V>
+struct lane_vec {
+    typedef T __attribute__((ext_vector_type(V))) type;
+};
+template <typename T>
+struct lane_vec<T, 1> {
+    typedef T type;
+};
+
+// Two line slots per thread (lines of at most 2^PAIR_LM points, where one slot leaves too few loads
+// in flight): the rows of both slots are loaded before either is solved and stored.  `two` is
+// false when the block has no second slot for this thread; the second slot then repeats the first
+// and is not stored.  The slots never overlap, so the in-place sweep stays exact.
+template <typename T, int LM, int EPI, int V>
+__device__ __forceinline__ void sweep_strided_pair(const DevPlan& P, const SweepArgs& A, const Strided& L1,
+                                                   const Strided& L2, bool two)
+{
+    typedef typename lane_vec<T, V>::type vt;
+    constexpr int M = 1 << LM;
+    const T* in = (const T*)A.in;
+    const T* f1 = (const T*)P.fac + L1.fac;
+    const T* f2 = (const T*)P.fac + L2.fac;
+    auto get = [&](int64_t idx) -> vt {
+        if constexpr (V == 1) return ld_stream(in + idx);
+        else return *(const vt*)(in + idx);
+    };
+    auto put = [&](int64_t idx, vt v) {
+        if constexpr (V == 1) {
+            sweep_store<T, EPI>(A, idx, v);
+        } else if constexpr (EPI == EPI_STORE) {
+            *(vt*)((T*)A.out + idx) = v;
+        } else {
+            vt* W = (vt*)((T*)A.out + idx);
+            st_stream(W, ld_stream(W) + (T)A.b1 * ld_stream((const vt*)((const T*)A.K1 + idx)) + (T)A.b2 * v);
+        }
+    };
+    vt d1[M], d2[M];
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        d1[r] = get(L1.base + r * L1.stride);
+        d2[r] = get(L2.base + r * L2.stride);
+    }
+#pragma unroll
+    for (int r = 0; r < M; ++r) {
+        if (r == 0) {
+            d1[0] = d1[0] * f1[0];
+            d2[0] = d2[0] * f2[0];
+        } else {
+            d1[r] = d1[r] * f1[r] - f1[M + r] * d1[r - 1];
+            d2[r] = d2[r] * f2[r] - f2[M + r] * d2[r - 1];
+        }
+    }
+#pragma unroll
+    for (int r = M - 2; r >= 0; --r) {
+        d1[r] = d1[r] - f1[2 * M + r] * d1[r + 1];
+        d2[r] = d2[r] - f2[2 * M + r] * d2[r + 1];
+    }
+#pragma unroll
+    for (int r = M - 1; r >= 0; --r) {
+        put(L1.base + r * L1.stride, d1[r]);
+        if (two) put(L2.base + r * L2.stride, d2[r]);
+    }
+}
+
 // Short strided lines (up to 2^SHORT_LM rows): one thread per B.vec adjacent lines (1, or
-// VW = 16 B / sizeof(T) when all the block's units allow it: one vector load and store per row).
+// VW = 16 B / sizeof(T) when all the block's units allow it: one vector load and store per row),
+// and per B.slots such slots (two for lines of at most 2^PAIR_LM points).
 template <typename T, int EPI>
 __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepArgs A, int axis, int64_t blk0)
 {
@@ -910,10 +975,41 @@ __global__ __launch_bounds__(LINE_BLOCK) void k_sweep_strided(DevPlan P, SweepAr
     if (gl >= B.line_end) return;
     const int64_t* lo = P.ax_line_off[axis];
     int k = B.k_start;
+    if constexpr (EPI == EPI_STORE) {
+        if (B.slots == 2) {                     // block-uniform; lines of at most 2^PAIR_LM points, axes 2..N-1
+            while (gl >= lo[k + 1]) ++k;
+            const Strided L = strided_geom(P, P.units[P.ax_units[axis][k]], axis, gl - lo[k], B.lm, A.run);
+            const int64_t gl2 = gl + (int64_t)LINE_BLOCK * B.vec;
+            const bool two = gl2 < B.line_end;
+            Strided L2 = L;
+            if (two) {
+                while (gl2 >= lo[k + 1]) ++k;
+                L2 = strided_geom(P, P.units[P.ax_units[axis][k]], axis, gl2 - lo[k], B.lm, A.run);
+            }
+            static_assert(PAIR_LM <= 2, "pair cases below");
+            if (B.vec == 1) {
+                switch (B.lm) {
+                case 0: sweep_strided_pair<T, 0, EPI, 1>(P, A, L, L2, two); break;
+                case 1: sweep_strided_pair<T, 1, EPI, 1>(P, A, L, L2, two); break;
+                case 2: sweep_strided_pair<T, 2, EPI, 1>(P, A, L, L2, two); break;
+                default: break;
+                }
+            } else {
+                switch (B.lm) {
+                case 0: sweep_strided_pair<T, 0, EPI, VW>(P, A, L, L2, two); break;
+                case 1: sweep_strided_pair<T, 1, EPI, VW>(P, A, L, L2, two); break;
+                case 2: sweep_strided_pair<T, 2, EPI, VW>(P, A, L, L2, two); break;
+                default: break;
+                }
+            }
+            return;
+        }
+    }
+    // one slot (the update form runs on the last axis only, whose blocks are never paired)
     while (gl >= lo[k + 1]) ++k;
     const UnitDev U = P.units[P.ax_units[axis][k]];
     const Strided L = strided_geom(P, U, axis, gl - lo[k], B.lm, A.run);
-    if (B.vec == 1) {                           // block-uniform
+    if (B.vec == 1) {                       // block-uniform
         switch (B.lm) {
         case 0: sweep_strided_reg<T, 0, EPI>(P, A, L); break;
         case 1: sweep_strided_reg<T, 1, EPI>(P, A, L); break;
@@ -965,15 +1061,6 @@ __device__ __forceinline__ T segment_carry(T a, T b, int seg, int nseg, int line
 }
 
 // Scalar or V-wide (ext_vector) element of the long-line solver.
-template <typename T, int V>
-struct lane_vec {
-    typedef T __attribute__((ext_vector_type(V))) type;
-};
-template <typename T>
-struct lane_vec<T, 1> {
-    typedef T type;
-};
-
 // Long strided line split into nseg = M/S segments of S = seg_rows consecutive rows, one per thread,
 // kept in VGPRs; with V > 1 the thread carries V adjacent lines (same factors) as one vector per
 // row.  Both Thomas recurrences are first order and linear, y_r = g_r inv_r - ainv_r y_{r-1} and
@@ -2164,7 +2251,8 @@ static void sweep_part(const DevPlan& P, int axis, int epi, const SweepArgs& a, 
 hipError_t launch_sweep(const DevPlan& P, int prec, int axis, int epi, int part, const SweepArgs& a,
                         hipStream_t s)
 {
-    if (axis == 0 && epi != EPI_STORE) return hipErrorInvalidValue;
+    // the update form runs on the last axis only (its short-line blocks hold one slot per thread)
+    if (epi != EPI_STORE && axis != P.d - 1) return hipErrorInvalidValue;
     const int64_t ns = P.ax_nblk_short[axis];
     const int64_t b0 = part == 0 ? 0 : ns;
     const int64_t nb = part == 0 ? ns : P.ax_nblk[axis] - ns;
