@@ -45,6 +45,11 @@ def _cases():
         # the standard technique at level 12: grids from 2^12 x 1 to 1 x 2^12 inner points
         "d2_standard_ct12": ([I.paper_caplet(sigma=0.3, phi=0.4)], I.combination(12, 0)),
         "d3_full_ragged": (d3[:1], I.full_grid([7, 0, 8])),
+        # 2- and 4-point lines on the middle axes (two line slots per thread of the short strided
+        # sweep): so few lines that no thread has a second slot, and enough that every thread has
+        # (the combination cases have blocks with both)
+        "d4_short_middle_axes": (d4[:1], I.full_grid([3, 1, 2, 1])),
+        "d4_short_middle_axes_full": (d4[:1], I.full_grid([5, 2, 1, 5])),
         "d2_standard_ct": ([I.paper_caplet(sigma=0.3, phi=0.4)], I.combination(6, 0)),
         "d3_ct": (d3, I.combination(4, 1)),
         "d4_ct": (d4, I.combination(4, 1)),
@@ -127,7 +132,8 @@ def test_axis_solves(name):
 
 
 @pytest.mark.parametrize("name", ["long_rate_axis", "long_v_axis", "very_long_v_axis", "longest_v_axis", "d4_ct",
-                                  "long_axis0_12", "long_axis0_15", "axis0_2e17", "v_axis_2e17"])
+                                  "d4_short_middle_axes_full", "long_axis0_12", "long_axis0_15", "axis0_2e17",
+                                  "v_axis_2e17"])
 def test_axis_solves_fp32(name):
     """a4/a10 in FP32 (factor tables computed in FP64, cast once): every line length class of the
     strided solvers, from register lines through the segmented solver to the memory path, against
